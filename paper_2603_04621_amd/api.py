@@ -1,0 +1,212 @@
+"""Python face of libdualip: marshals numpy/torch arrays into the C ABI.
+
+Every computation runs in the HIP library; this module only builds the
+descriptors, hands over device pointers (torch tensors on the current ROCm
+device) and the current HIP stream, and checks status codes.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class _HostDesc:
+    """Keeps the contiguous host arrays alive while the descriptor is in use."""
+
+    def __init__(self, inst, layout: str = "csc"):
+        self.m, self.n = int(inst.m), int(inst.n)
+        if layout == "csc":
+            self.ptr = None
+            self.idx = np.ascontiguousarray(inst.dst, dtype=np.int32)
+            self.val = np.ascontiguousarray(inst.a, dtype=np.float64)
+            lay = L.DL_CSC
+        elif layout == "csr":
+            rp, ci, v = inst.csr()
+            self.ptr = np.ascontiguousarray(rp, dtype=np.int64)
+            self.idx = np.ascontiguousarray(ci, dtype=np.int32)
+            self.val = np.ascontiguousarray(v, dtype=np.float64)
+            lay = L.DL_CSR
+        else:
+            raise ValueError(layout)
+        self.c = np.ascontiguousarray(inst.c, dtype=np.float64)
+        self.b = np.ascontiguousarray(inst.b, dtype=np.float64)
+        self.block_off = np.ascontiguousarray(inst.block_off, dtype=np.int64)
+        self.block_proj = np.ascontiguousarray(inst.block_proj, dtype=np.uint8)
+        self.upper = None if inst.upper is None else np.ascontiguousarray(inst.upper, np.float64)
+        self.desc = L.ProblemDesc(self.m, self.n, self.idx.shape[0], lay, _np_ptr(self.ptr),
+                                  _np_ptr(self.idx), _np_ptr(self.val), _np_ptr(self.c),
+                                  _np_ptr(self.b), self.block_off.shape[0] - 1,
+                                  _np_ptr(self.block_off), _np_ptr(self.block_proj),
+                                  _np_ptr(self.upper))
+
+
+def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: int = 0, v=None):
+    o = L.ProblemOpts()
+    L.lib().dl_problem_opts_init(ctypes.byref(o))
+    o.storage = L.STORAGE[storage]
+    o.row_normalize = 1 if row_normalize else 0
+    o.primal_scale = int(primal_scale)
+    keep = None
+    if v is not None:
+        keep = np.ascontiguousarray(v, dtype=np.float64)
+        o.v = keep.ctypes.data
+    return o, keep
+
+
+def validate(inst, layout: str = "csc", **opts) -> int:
+    """dl_problem_validate (host only).  Returns the status code."""
+    hd = _HostDesc(inst, layout)
+    o, _keep = make_opts(**opts)
+    return L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o))
+
+
+@dataclass
+class SolveSettings:
+    """Mirrors dl_solve_opts (include/dualip.h)."""
+    gamma0: float = 0.01
+    gamma_final: float = 0.01
+    n_stages: int = 1
+    momentum: int = 1
+    stage_iters: int = 0
+    stage_tol: float = 0.0
+    tol_rel_gap: float = 1e-4
+    max_iters: int = 10000
+    check_every: int = 10
+    max_step: float = 0.01
+    init_step: float = 1e-4
+    adaptive: int = 1
+    warm_start: int = 0
+    graph_iters: int = 0
+    time_kernels: int = 0
+    trace: bool = False
+
+    def to_c(self, trace_buf=None) -> L.SolveOpts:
+        o = L.SolveOpts()
+        L.lib().dl_solve_opts_init(ctypes.byref(o))
+        for k in ("gamma0", "gamma_final", "n_stages", "momentum", "stage_iters", "stage_tol",
+                  "tol_rel_gap", "max_iters", "check_every", "max_step", "init_step",
+                  "adaptive", "warm_start", "graph_iters", "time_kernels"):
+            setattr(o, k, getattr(self, k))
+        o.trace_host = None if trace_buf is None else trace_buf.ctypes.data
+        return o
+
+
+@dataclass
+class SolveOutcome:
+    status: int
+    converged: bool
+    stage: int
+    iters: int
+    gamma: float
+    g: float
+    P: float
+    rel_gap: float
+    max_infeas: float
+    seconds: float
+    grad_kernel_ms: float
+    grad_launches: int
+    trace: Optional[np.ndarray] = field(default=None, repr=False)
+
+
+def outcome(r: L.SolveResult, trace=None) -> SolveOutcome:
+    return SolveOutcome(r.status, bool(r.converged), r.stage, r.iters, r.gamma, r.g, r.P,
+                        r.rel_gap, r.max_infeas, r.seconds, r.grad_kernel_ms, r.grad_launches,
+                        None if trace is None else trace[: r.iters])
+
+
+class Problem:
+    """A matching LP created on the current HIP device (dl_problem_create)."""
+
+    def __init__(self, inst, storage: str = "f32", row_normalize: bool = True,
+                 primal_scale: int = 0, v=None, layout: str = "csc", stream=None):
+        import torch
+        self.m, self.n = int(inst.m), int(inst.n)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        hd = _HostDesc(inst, layout)
+        o, _keep = make_opts(storage, row_normalize, primal_scale, v)
+        h = ctypes.c_void_p()
+        L.check(L.lib().dl_problem_create(ctypes.byref(hd.desc), ctypes.byref(o),
+                                          _stream(stream), ctypes.byref(h)), "dl_problem_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = L.ProblemInfo()
+        L.check(L.lib().dl_problem_get_info(self._h, ctypes.byref(i)), "dl_problem_get_info")
+        return {k: getattr(i, k) for k, _ in L.ProblemInfo._fields_}
+
+    def dual_grad(self, lam, gamma: float, want_x: bool = False, want_eval: bool = False,
+                  stream=None):
+        """(grad [m] fp64 tensor, x [n] or None, dict of scalars or None)."""
+        import torch
+        lam = lam.to(device=self.device, dtype=torch.float64).contiguous()
+        grad = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_x else None
+        ev = L.Eval() if want_eval else None
+        L.check(L.lib().dl_dual_grad(self._h, lam.data_ptr(), float(gamma), grad.data_ptr(),
+                                     None if x is None else x.data_ptr(),
+                                     ctypes.byref(ev) if ev is not None else None,
+                                     _stream(stream)), "dl_dual_grad")
+        evd = None if ev is None else {k: getattr(ev, k) for k, _ in L.Eval._fields_}
+        return grad, x, evd
+
+    def time_grad_kernel(self, lam, gamma: float, iters: int = 10, check: bool = False,
+                         stream=None) -> float:
+        import torch
+        lam = lam.to(device=self.device, dtype=torch.float64).contiguous()
+        ms = ctypes.c_double()
+        L.check(L.lib().dl_time_grad_kernel(self._h, lam.data_ptr(), float(gamma), int(iters),
+                                            1 if check else 0, ctypes.byref(ms), _stream(stream)),
+                "dl_time_grad_kernel")
+        return ms.value
+
+    def solve(self, settings: SolveSettings, lam0=None, stream=None):
+        """(lam tensor [m], SolveOutcome); lam0 warm-starts when given."""
+        import torch
+        lam = torch.zeros(self.m, dtype=torch.float64, device=self.device)
+        st = SolveSettings(**{**settings.__dict__})
+        if lam0 is not None:
+            lam.copy_(lam0.to(device=self.device, dtype=torch.float64))
+            st.warm_start = 1
+        tr = np.full((max(st.max_iters, 1), L.DL_TRACE_W), np.nan) if st.trace else None
+        o = st.to_c(tr)
+        r = L.SolveResult()
+        L.check(L.lib().dl_solve(self._h, ctypes.byref(o), lam.data_ptr(), ctypes.byref(r),
+                                 _stream(stream)),
+                "dl_solve", ok=(L.DL_OK, L.DL_ERR_NOT_CONVERGED))
+        return lam, outcome(r, tr)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().dl_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,776 @@
+// C ABI of libdualip: validation, create-time layout, dual evaluation and the
+// single-problem solve loop.  See include/dualip.h for the contract.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "problem.hpp"
+
+using namespace dl;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace dlh {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+dl_status hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? DL_ERR_OUT_OF_MEMORY : DL_ERR_DEVICE;
+}
+
+}  // namespace dlh
+
+using dlh::set_error;
+using dlh::hip_fail;
+
+#define HIP_TRY(call, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, what);      \
+    } while (0)
+
+extern "C" const char* dl_last_error(void) { return dlh::g_err.c_str(); }
+
+extern "C" const char* dl_status_str(dl_status s)
+{
+    switch (s) {
+    case DL_OK: return "ok";
+    case DL_ERR_INVALID_ARG: return "invalid argument";
+    case DL_ERR_UNSUPPORTED: return "unsupported";
+    case DL_ERR_OUT_OF_MEMORY: return "out of memory";
+    case DL_ERR_DEVICE: return "device error";
+    case DL_ERR_NUMERIC: return "numeric error";
+    case DL_ERR_NOT_CONVERGED: return "not converged";
+    case DL_ERR_BUSY: return "busy";
+    case DL_ERR_NOT_FOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+extern "C" void dl_problem_opts_init(dl_problem_opts* o)
+{
+    if (!o) return;
+    o->storage = DL_F32;
+    o->row_normalize = 1;
+    o->primal_scale = 0;
+    o->v = nullptr;
+}
+
+extern "C" void dl_solve_opts_init(dl_solve_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->gamma0 = 0.01;
+    o->gamma_final = 0.01;
+    o->n_stages = 1;
+    o->momentum = 1;
+    o->stage_iters = 0;
+    o->stage_tol = 0.0;
+    o->tol_rel_gap = 1e-4;
+    o->max_iters = 10000;
+    o->check_every = 10;
+    o->max_step = 0.01;
+    o->init_step = 1e-4;
+    o->adaptive = 1;
+    o->warm_start = 0;
+    o->graph_iters = 0;
+    o->time_kernels = 0;
+    o->trace_host = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// validation (host only)
+// ---------------------------------------------------------------------------
+static bool finite_all(const double* v, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* o, int* solve_ok)
+{
+    if (!d) { set_error("desc is NULL"); return DL_ERR_INVALID_ARG; }
+    if (d->m < 1 || d->m >= (int64_t)1 << 28) { set_error("m must be in [1, 2^28)"); return DL_ERR_INVALID_ARG; }
+    if (d->n < 0 || d->nnz < 0) { set_error("n and nnz must be >= 0"); return DL_ERR_INVALID_ARG; }
+    if (d->layout != DL_CSC && d->layout != DL_CSR) { set_error("unknown layout %d", (int)d->layout); return DL_ERR_INVALID_ARG; }
+    if (d->nnz > 0 && (!d->idx || !d->val)) { set_error("idx/val are NULL"); return DL_ERR_INVALID_ARG; }
+    if (d->n > 0 && !d->c) { set_error("c is NULL"); return DL_ERR_INVALID_ARG; }
+    if (!d->b) { set_error("b is NULL"); return DL_ERR_INVALID_ARG; }
+    if (d->num_blocks < 0 || !d->block_off) { set_error("blocks missing"); return DL_ERR_INVALID_ARG; }
+    if (d->num_blocks > 0 && !d->block_proj) { set_error("block_proj is NULL"); return DL_ERR_INVALID_ARG; }
+    if (d->block_off[0] != 0 || d->block_off[d->num_blocks] != d->n) {
+        set_error("block_off must start at 0 and end at n"); return DL_ERR_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < d->num_blocks; ++i) {
+        if (d->block_off[i + 1] < d->block_off[i]) { set_error("block_off decreases at %lld", (long long)i); return DL_ERR_INVALID_ARG; }
+        if (d->block_proj[i] > 1) { set_error("block_proj[%lld] = %d is not a dl_proj", (long long)i, (int)d->block_proj[i]); return DL_ERR_INVALID_ARG; }
+        if (d->block_off[i + 1] - d->block_off[i] >= (int64_t)1 << 31) { set_error("block too large"); return DL_ERR_UNSUPPORTED; }
+    }
+    if (!finite_all(d->val, d->nnz)) { set_error("val has a non-finite entry"); return DL_ERR_INVALID_ARG; }
+    if (!finite_all(d->c, d->n)) { set_error("c has a non-finite entry"); return DL_ERR_INVALID_ARG; }
+    if (!finite_all(d->b, d->m)) { set_error("b has a non-finite entry"); return DL_ERR_INVALID_ARG; }
+    if (d->upper)
+        for (int64_t e = 0; e < d->n; ++e)
+            if (std::isnan(d->upper[e]) || d->upper[e] < 0.0) { set_error("upper[%lld] must be >= 0", (long long)e); return DL_ERR_INVALID_ARG; }
+    if (d->layout == DL_CSC) {
+        if (!d->ptr) {
+            if (d->nnz != d->n) { set_error("CSC with ptr = NULL needs nnz == n"); return DL_ERR_INVALID_ARG; }
+        } else {
+            if (d->ptr[0] != 0 || d->ptr[d->n] != d->nnz) { set_error("CSC ptr must run from 0 to nnz"); return DL_ERR_INVALID_ARG; }
+            for (int64_t e = 0; e < d->n; ++e) {
+                const int64_t k = d->ptr[e + 1] - d->ptr[e];
+                if (k < 0) { set_error("CSC ptr decreases at column %lld", (long long)e); return DL_ERR_INVALID_ARG; }
+                if (k > 1) { set_error("column %lld has %lld entries: only one matching family is supported", (long long)e, (long long)k); return DL_ERR_UNSUPPORTED; }
+            }
+        }
+        for (int64_t k = 0; k < d->nnz; ++k)
+            if (d->idx[k] < 0 || d->idx[k] >= d->m) { set_error("row index %d out of range at %lld", d->idx[k], (long long)k); return DL_ERR_INVALID_ARG; }
+    } else {
+        if (!d->ptr) { set_error("CSR needs ptr"); return DL_ERR_INVALID_ARG; }
+        if (d->ptr[0] != 0 || d->ptr[d->m] != d->nnz) { set_error("CSR ptr must run from 0 to nnz"); return DL_ERR_INVALID_ARG; }
+        for (int64_t j = 0; j < d->m; ++j)
+            if (d->ptr[j + 1] < d->ptr[j]) { set_error("CSR ptr decreases at row %lld", (long long)j); return DL_ERR_INVALID_ARG; }
+        std::vector<uint8_t> seen((size_t)d->n, 0);
+        for (int64_t k = 0; k < d->nnz; ++k) {
+            const int32_t e = d->idx[k];
+            if (e < 0 || e >= d->n) { set_error("column index %d out of range at %lld", e, (long long)k); return DL_ERR_INVALID_ARG; }
+            if (seen[e]) { set_error("column %d has several entries: only one matching family is supported", e); return DL_ERR_UNSUPPORTED; }
+            seen[e] = 1;
+        }
+    }
+    if (o) {
+        if (o->storage < DL_F64 || o->storage > DL_BF16_AC) { set_error("unknown storage %d", (int)o->storage); return DL_ERR_INVALID_ARG; }
+        if (o->row_normalize != 0 && o->row_normalize != 1) { set_error("row_normalize must be 0 or 1"); return DL_ERR_INVALID_ARG; }
+        if (o->primal_scale < 0 || o->primal_scale > 2) { set_error("primal_scale must be 0, 1 or 2"); return DL_ERR_INVALID_ARG; }
+        if (o->primal_scale == 2) {
+            if (!o->v) { set_error("primal_scale = 2 needs v"); return DL_ERR_INVALID_ARG; }
+            for (int64_t e = 0; e < d->n; ++e)
+                if (!(o->v[e] > 0.0) || !std::isfinite(o->v[e])) { set_error("v[%lld] must be positive and finite", (long long)e); return DL_ERR_INVALID_ARG; }
+        }
+    }
+    int ok = 1;
+    for (int64_t k = 0; k < d->nnz && ok; ++k) ok = d->val[k] >= 0.0;
+    for (int64_t j = 0; j < d->m && ok; ++j) ok = d->b[j] >= 0.0;
+    if (solve_ok) *solve_ok = ok;
+    return DL_OK;
+}
+
+extern "C" dl_status dl_problem_validate(const dl_problem_desc* d, const dl_problem_opts* o)
+{
+    return validate_impl(d, o, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// create: host layout
+// ---------------------------------------------------------------------------
+static uint16_t to_bf16(double x)
+{
+    const float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+template <typename F>
+static void parallel_for(int64_t n, int64_t grain, F f)
+{
+    int nt = (int)std::min<int64_t>(16, std::max<int64_t>(1, n / std::max<int64_t>(grain, 1)));
+    nt = std::max(1, std::min<int>(nt, (int)std::thread::hardware_concurrency()));
+    if (nt <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        th.emplace_back([=]() { f(lo, hi); });
+    }
+    for (auto& x : th) x.join();
+}
+
+struct HostLayout {
+    std::vector<Item> items;
+    std::vector<Chunk> chunks;
+    std::vector<int64_t> src;      // stream position -> original column
+    int64_t nA = 0, nB = 0;        // wave items / workgroup items
+    int64_t n_lane = 0, n_wave = 0, n_wg = 0;
+};
+
+// Groups blocks by (kind, projection, degree), assigns stream positions and
+// splits the work into nchunks ranges balanced by nonzeros.
+static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, HostLayout& L)
+{
+    const int64_t I = d->num_blocks;
+    // bucket keys: lane kinds by (proj, d), then wave kinds by (proj, d), then wg by proj
+    std::vector<std::vector<int64_t>> lane(2 * (kLaneMaxDeg + 1));
+    std::vector<std::pair<int64_t, int64_t>> wave, wgb;   // (key, block)
+    for (int64_t i = 0; i < I; ++i) {
+        const int64_t deg = d->block_off[i + 1] - d->block_off[i];
+        const int pr = d->block_proj[i];
+        if (deg == 0) continue;
+        if (deg <= lane_max) lane[(size_t)pr * (kLaneMaxDeg + 1) + deg].push_back(i);
+        else if (deg <= kWaveMaxDeg) wave.push_back({(int64_t)pr * (kWaveMaxDeg + 1) + deg, i});
+        else wgb.push_back({(int64_t)pr, i});
+    }
+    std::stable_sort(wave.begin(), wave.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    std::stable_sort(wgb.begin(), wgb.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    int64_t pos = 0;
+    struct Src { int64_t item; std::vector<int64_t> blocks; };
+    std::vector<std::pair<int64_t, int64_t>> group_blocks;   // item -> [start, end) in gb
+    std::vector<int64_t> gb;
+    for (int pr = 0; pr < 2; ++pr)
+        for (int deg = 1; deg <= kLaneMaxDeg; ++deg) {
+            const auto& v = lane[(size_t)pr * (kLaneMaxDeg + 1) + deg];
+            for (size_t s0 = 0; s0 < v.size(); s0 += 64) {
+                const int nb = (int)std::min<size_t>(64, v.size() - s0);
+                Item it;
+                it.base = pos;
+                it.d = deg;
+                it.nb = (uint16_t)nb;
+                it.kind = ITEM_LANE;
+                it.proj = (uint8_t)pr;
+                L.items.push_back(it);
+                group_blocks.push_back({(int64_t)gb.size(), (int64_t)gb.size() + nb});
+                for (int l = 0; l < nb; ++l) gb.push_back(v[s0 + l]);
+                pos += (int64_t)nb * deg;
+                ++L.n_lane;
+            }
+        }
+    for (auto& kv : wave) {
+        const int64_t i = kv.second;
+        Item it;
+        it.base = pos;
+        it.d = (int32_t)(d->block_off[i + 1] - d->block_off[i]);
+        it.nb = 1;
+        it.kind = ITEM_WAVE;
+        it.proj = d->block_proj[i];
+        L.items.push_back(it);
+        group_blocks.push_back({(int64_t)gb.size(), (int64_t)gb.size() + 1});
+        gb.push_back(i);
+        pos += it.d;
+        ++L.n_wave;
+    }
+    L.nA = (int64_t)L.items.size();
+    for (auto& kv : wgb) {
+        const int64_t i = kv.second;
+        Item it;
+        it.base = pos;
+        it.d = (int32_t)(d->block_off[i + 1] - d->block_off[i]);
+        it.nb = 1;
+        it.kind = ITEM_WG;
+        it.proj = d->block_proj[i];
+        L.items.push_back(it);
+        group_blocks.push_back({(int64_t)gb.size(), (int64_t)gb.size() + 1});
+        gb.push_back(i);
+        pos += it.d;
+        ++L.n_wg;
+    }
+    L.nB = (int64_t)L.items.size() - L.nA;
+    // stream position -> original column
+    L.src.assign((size_t)pos, 0);
+    const int64_t nit = (int64_t)L.items.size();
+    parallel_for(nit, 4096, [&](int64_t lo, int64_t hi) {
+        for (int64_t q = lo; q < hi; ++q) {
+            const Item& it = L.items[q];
+            const int64_t g0 = group_blocks[q].first;
+            if (it.kind == ITEM_LANE) {
+                for (int l = 0; l < it.nb; ++l) {
+                    const int64_t c0 = d->block_off[gb[g0 + l]];
+                    for (int k = 0; k < it.d; ++k) L.src[it.base + (int64_t)k * it.nb + l] = c0 + k;
+                }
+            } else {
+                const int64_t c0 = d->block_off[gb[g0]];
+                for (int k = 0; k < it.d; ++k) L.src[it.base + k] = c0 + k;
+            }
+        }
+    });
+    // chunks: each kind list split by nonzeros
+    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0});
+    auto split = [&](int64_t first, int64_t count, bool a) {
+        std::vector<int64_t> pre((size_t)count + 1, 0);
+        for (int64_t q = 0; q < count; ++q)
+            pre[q + 1] = pre[q] + (int64_t)L.items[first + q].d * L.items[first + q].nb;
+        const int64_t tot = pre[count];
+        int64_t q = 0;
+        for (int c = 0; c < nchunks; ++c) {
+            const int64_t target = (int64_t)((double)tot * (c + 1) / nchunks);
+            const int64_t q0 = q;
+            while (q < count && (c == nchunks - 1 || pre[q] + (pre[q + 1] - pre[q]) / 2 < target)) ++q;
+            if (a) { L.chunks[c].a0 = (int32_t)(first + q0); L.chunks[c].a1 = (int32_t)(first + q); }
+            else { L.chunks[c].b0 = (int32_t)(first + q0); L.chunks[c].b1 = (int32_t)(first + q); }
+        }
+    };
+    split(0, L.nA, true);
+    split(L.nA, L.nB, false);
+}
+
+static int device_cus(int dev)
+{
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    return v;
+}
+
+static size_t device_max_lds(int dev)
+{
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        v = 65536;
+    return (size_t)v;
+}
+
+template <typename T>
+static dl_status dalloc(dl_problem* p, T** ptr, size_t count, const char* what)
+{
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of %zu bytes for %s failed: %s", count * sizeof(T), what, hipGetErrorString(e));
+        return DL_ERR_OUT_OF_MEMORY;
+    }
+    p->allocs.push_back(q);
+    p->device_bytes += count * sizeof(T);
+    *ptr = (T*)q;
+    return DL_OK;
+}
+
+static void free_problem(dl_problem* p)
+{
+    if (!p) return;
+    for (void* q : p->allocs) (void)hipFree(q);
+    if (p->st_host) (void)hipHostFree(p->st_host);
+    delete p;
+}
+
+extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_problem_opts* opts_in,
+                                       void* hip_stream, dl_problem** out)
+{
+    if (!out) { set_error("out is NULL"); return DL_ERR_INVALID_ARG; }
+    *out = nullptr;
+    dl_problem_opts opts;
+    dl_problem_opts_init(&opts);
+    if (opts_in) opts = *opts_in;
+    int solve_ok = 1;
+    dl_status st = validate_impl(d, &opts, &solve_ok);
+    if (st != DL_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    const int64_t m = d->m, n = d->n;
+    dl_problem* p = new dl_problem();
+    HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
+    p->m = m;
+    p->n = n;
+    p->nblocks = d->num_blocks;
+    p->storage = opts.storage;
+    p->solve_ok = solve_ok;
+    p->J = (int)m;
+
+    // per column: row and value of its single entry (empty column: row 0, a = 0)
+    std::vector<int32_t> crow((size_t)n, 0);
+    std::vector<double> cval((size_t)n, 0.0);
+    if (d->layout == DL_CSC) {
+        for (int64_t e = 0; e < n; ++e) {
+            const int64_t lo = d->ptr ? d->ptr[e] : e, hi = d->ptr ? d->ptr[e + 1] : e + 1;
+            if (hi > lo) { crow[e] = d->idx[lo]; cval[e] = d->val[lo]; }
+        }
+    } else {
+        for (int64_t j = 0; j < m; ++j)
+            for (int64_t k = d->ptr[j]; k < d->ptr[j + 1]; ++k) { crow[d->idx[k]] = (int32_t)j; cval[d->idx[k]] = d->val[k]; }
+    }
+    // primal scale v (regularizer gamma/2 v^2 x^2) and Jacobi row scale of A D_v^{-1}
+    std::vector<double> v2;
+    if (opts.primal_scale != 0) {
+        v2.resize((size_t)n);
+        for (int64_t e = 0; e < n; ++e) {
+            double v = opts.primal_scale == 1 ? std::fabs(cval[e]) : opts.v[e];
+            if (!(v > 0.0)) v = 1.0;
+            v2[e] = v * v;
+        }
+        p->has_w = 1;
+    }
+    std::vector<double> r2((size_t)m, 0.0);
+    std::vector<int64_t> rdeg((size_t)m, 0);
+    for (int64_t e = 0; e < n; ++e) {
+        const double z = cval[e];
+        r2[crow[e]] += p->has_w ? z * z / v2[e] : z * z;
+        rdeg[crow[e]] += 1;
+    }
+    // relabel rows by descending degree (ties by index): hot rows first
+    std::vector<int32_t> orig((size_t)m), newid((size_t)m);
+    std::iota(orig.begin(), orig.end(), 0);
+    std::stable_sort(orig.begin(), orig.end(), [&](int32_t a, int32_t b) { return rdeg[a] > rdeg[b]; });
+    for (int64_t j = 0; j < m; ++j) newid[orig[j]] = (int32_t)j;
+    std::vector<double> bD((size_t)m), Dv((size_t)m);
+    for (int64_t j = 0; j < m; ++j) {
+        const int32_t o = orig[j];
+        bD[j] = d->b[o];
+        Dv[j] = (opts.row_normalize && r2[o] > 0.0) ? 1.0 / std::sqrt(r2[o]) : 1.0;
+    }
+    for (int64_t i = 0; i < d->num_blocks && !p->has_box; ++i) p->has_box = d->block_proj[i] == DL_PROJ_BOX;
+
+    // work items and chunks
+    const int cus = device_cus(p->device);
+    int nch = (int)std::min<int64_t>(cus, std::max<int64_t>(1, (n + 32767) / 32768));
+    HostLayout L;
+    build_items(d, nch, opts.storage == DL_F64 ? kLaneMaxDegF64 : kLaneMaxDeg, L);
+    p->nchunks = nch;
+    p->nitems = (int)L.items.size();
+    p->n_lane = L.n_lane;
+    p->n_wave = L.n_wave;
+    p->n_wg = L.n_wg;
+    const size_t max_lds = device_max_lds(p->device);
+    int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
+    p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
+    p->nblk2 = (p->J + 63) / 64;
+
+    // stream arrays
+    const size_t es = opts.storage == DL_F64 ? 8 : (opts.storage == DL_F32 ? 4 : 2);
+    std::vector<unsigned char> Ah((size_t)n * es), Ch((size_t)n * es);
+    std::vector<int32_t> dsth((size_t)n);
+    std::vector<float> Uh(p->has_box ? (size_t)n : 0), IVh(p->has_w ? (size_t)n : 0);
+    int64_t box_edges = 0;
+    {
+        std::vector<uint8_t> ebox;
+        if (p->has_box) {
+            ebox.assign((size_t)n, 0);
+            for (int64_t i = 0; i < d->num_blocks; ++i)
+                if (d->block_proj[i] == DL_PROJ_BOX)
+                    for (int64_t e = d->block_off[i]; e < d->block_off[i + 1]; ++e) ebox[e] = 1;
+        }
+        parallel_for(n, 1 << 20, [&](int64_t lo, int64_t hi) {
+            for (int64_t q = lo; q < hi; ++q) {
+                const int64_t e = L.src[q];
+                const double a = cval[e], c = d->c[e];
+                if (opts.storage == DL_F64) { ((double*)Ah.data())[q] = a; ((double*)Ch.data())[q] = c; }
+                else if (opts.storage == DL_F32) { ((float*)Ah.data())[q] = (float)a; ((float*)Ch.data())[q] = (float)c; }
+                else { ((uint16_t*)Ah.data())[q] = to_bf16(a); ((uint16_t*)Ch.data())[q] = to_bf16(c); }
+                dsth[q] = newid[crow[e]];
+                if (p->has_box) Uh[q] = (float)(d->upper ? d->upper[e] : 1.0);
+                if (p->has_w) IVh[q] = (float)(1.0 / v2[e]);
+            }
+        });
+        if (p->has_box)
+            for (int64_t e = 0; e < n; ++e) box_edges += ebox[e];
+    }
+    p->stream_bytes = n * (int64_t)(2 * es + 4) + (p->has_box ? 4 * box_edges : 0) + (p->has_w ? 4 * n : 0);
+
+    // device allocation and upload
+#define ALLOC(ptr, count, what)                                      \
+    do {                                                             \
+        st = dalloc(p, &(ptr), (count), what);                       \
+        if (st != DL_OK) { free_problem(p); return st; }             \
+    } while (0)
+#define UP(dstp, srcp, bytes, what)                                                          \
+    do {                                                                                     \
+        hipError_t e_ = hipMemcpyAsync((dstp), (srcp), (bytes), hipMemcpyHostToDevice, s);   \
+        if (e_ != hipSuccess) { st = hip_fail(e_, what); free_problem(p); return st; }       \
+    } while (0)
+    unsigned char *Ad, *Cd;
+    ALLOC(Ad, (size_t)n * es, "a");
+    ALLOC(Cd, (size_t)n * es, "c");
+    p->A = Ad;
+    p->C = Cd;
+    ALLOC(p->dst, (size_t)n, "dst");
+    if (p->has_box) ALLOC(p->U, (size_t)n, "upper");
+    if (p->has_w) ALLOC(p->IV, (size_t)n, "primal scale");
+    ALLOC(p->perm, (size_t)n, "perm");
+    ALLOC(p->items, L.items.size(), "items");
+    ALLOC(p->chunks, L.chunks.size(), "chunks");
+    ALLOC(p->b, (size_t)m, "b");
+    ALLOC(p->D, (size_t)m, "D");
+    ALLOC(p->orig, (size_t)m, "orig");
+    ALLOC(p->part, (size_t)3 * nch * std::max(1, p->K), "partials");
+    ALLOC(p->tail, (size_t)3 * m, "tail");
+    ALLOC(p->obj_part, (size_t)3 * nch, "objective partials");
+    ALLOC(p->blockpart, (size_t)p->nblk2 * kRedStride, "block partials");
+    ALLOC(p->lam_int, (size_t)m, "lambda");
+    ALLOC(p->eval6, 8, "eval");
+    ALLOC(p->lam, (size_t)m, "lam");
+    ALLOC(p->y, (size_t)m, "y");
+    ALLOC(p->yp, (size_t)m, "y_prev");
+    ALLOC(p->G, (size_t)m, "G");
+    ALLOC(p->Gp, (size_t)m, "G_prev");
+    ALLOC(p->lam_eval, (size_t)m, "lam_eval");
+    ALLOC(p->st, 1, "state");
+    UP(p->A, Ah.data(), Ah.size(), "upload a");
+    UP(p->C, Ch.data(), Ch.size(), "upload c");
+    UP(p->dst, dsth.data(), dsth.size() * 4, "upload dst");
+    if (p->has_box) UP(p->U, Uh.data(), Uh.size() * 4, "upload upper");
+    if (p->has_w) UP(p->IV, IVh.data(), IVh.size() * 4, "upload scale");
+    UP(p->perm, L.src.data(), L.src.size() * 8, "upload perm");
+    UP(p->items, L.items.data(), L.items.size() * sizeof(Item), "upload items");
+    UP(p->chunks, L.chunks.data(), L.chunks.size() * sizeof(Chunk), "upload chunks");
+    UP(p->b, bD.data(), (size_t)m * 8, "upload b");
+    UP(p->D, Dv.data(), (size_t)m * 8, "upload D");
+    UP(p->orig, orig.data(), (size_t)m * 4, "upload orig");
+    {
+        hipError_t e = hipMemsetAsync(p->tail, 0, (size_t)3 * m * sizeof(double), s);
+        if (e != hipSuccess) { st = hip_fail(e, "clear tail"); free_problem(p); return st; }
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { st = hip_fail(e, "upload"); free_problem(p); return st; }
+        e = hipHostMalloc((void**)&p->st_host, 2 * sizeof(SolveState), hipHostMallocDefault);
+        if (e != hipSuccess) { p->st_host = nullptr; st = hip_fail(e, "pinned state"); free_problem(p); return st; }
+        e = set_grad_attributes(std::max(grad_lds_bytes(p->K, false), grad_lds_bytes(p->K, true)));
+        if (e != hipSuccess) { st = hip_fail(e, "kernel LDS attribute"); free_problem(p); return st; }
+    }
+#undef ALLOC
+#undef UP
+    *out = p;
+    return DL_OK;
+}
+
+extern "C" dl_status dl_problem_destroy(dl_problem* p)
+{
+    if (!p) return DL_OK;
+    (void)hipDeviceSynchronize();
+    free_problem(p);
+    return DL_OK;
+}
+
+extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info)
+{
+    if (!p || !info) { set_error("NULL argument"); return DL_ERR_INVALID_ARG; }
+    info->m = p->m;
+    info->n = p->n;
+    info->num_blocks = p->nblocks;
+    info->lane_groups = p->n_lane;
+    info->wave_blocks = p->n_wave;
+    info->wg_blocks = p->n_wg;
+    info->chunks = p->nchunks;
+    info->lds_rows = p->K;
+    info->stream_bytes = p->stream_bytes;
+    info->device_bytes = (int64_t)p->device_bytes;
+    info->storage = p->storage;
+    info->has_box = p->has_box;
+    return DL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument blocks
+// ---------------------------------------------------------------------------
+namespace dlh {
+
+GradArgs grad_args(const dl_problem* p, const double* lam, const double* gamma_ptr, double gamma_val,
+                   const int32_t* done, double* X)
+{
+    GradArgs g;
+    std::memset(&g, 0, sizeof g);
+    g.A = p->A;
+    g.C = p->C;
+    g.dst = p->dst;
+    g.U = p->U;
+    g.IV = p->IV;
+    g.perm = p->perm;
+    g.X = X;
+    g.items = p->items;
+    g.chunks = p->chunks;
+    g.lam = lam;
+    g.gamma_ptr = gamma_ptr;
+    g.gamma_val = gamma_val;
+    g.done = done;
+    g.J = p->J;
+    g.K = p->K;
+    g.nchunks = p->nchunks;
+    g.part = p->part;
+    g.tail = p->tail;
+    g.obj_part = p->obj_part;
+    return g;
+}
+
+ReduceArgs reduce_args(const dl_problem* p, int check, int mode, const double* lam,
+                       const double* gamma_ptr, double gamma_val, const int32_t* done, double* grad_out)
+{
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.part = p->part;
+    r.nchunks = p->nchunks;
+    r.K = p->K;
+    r.J = p->J;
+    r.check = check;
+    r.mode = mode;
+    r.tail = p->tail;
+    r.b = p->b;
+    r.D = p->D;
+    r.lam = lam;
+    r.y = p->y;
+    r.yp = p->yp;
+    r.Gp = p->Gp;
+    r.G = p->G;
+    r.orig = p->orig;
+    r.grad_out = grad_out;
+    r.gamma_ptr = gamma_ptr;
+    r.gamma_val = gamma_val;
+    r.done = done;
+    r.blockpart = p->blockpart;
+    return r;
+}
+
+AgdArgs agd_args(const dl_problem* p, const SolveParams& prm, int check, double* trace)
+{
+    AgdArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.st = p->st;
+    a.prm = prm;
+    a.check = check;
+    a.nchunks = p->nchunks;
+    a.nblk = p->nblk2;
+    a.J = p->J;
+    a.obj_part = p->obj_part;
+    a.blockpart = p->blockpart;
+    a.lam = p->lam;
+    a.y = p->y;
+    a.yp = p->yp;
+    a.G = p->G;
+    a.Gp = p->Gp;
+    a.lam_eval = p->lam_eval;
+    a.D = p->D;
+    a.trace = trace;
+    return a;
+}
+
+hipError_t enqueue_iteration(dl_problem* p, const SolveParams& prm, int check, double* trace, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1)
+{
+    const double* gptr = &p->st->gamma;
+    const int32_t* done = &p->st->done;
+    GradArgs g = grad_args(p, p->lam_eval, gptr, 0.0, done, nullptr);
+    hipError_t e;
+    if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+    if ((e = launch_grad(g, p->storage, check != 0, p->has_w != 0, s)) != hipSuccess) return e;
+    if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
+    ReduceArgs r = reduce_args(p, check, 0, p->lam_eval, gptr, 0.0, done, nullptr);
+    if ((e = launch_reduce(r, p->nblk2, s)) != hipSuccess) return e;
+    AgdArgs a = agd_args(p, prm, check, trace);
+    return launch_agd(a, s);
+}
+
+dl_status check_solve_opts(const dl_solve_opts* o)
+{
+    if (!o) { set_error("opts is NULL"); return DL_ERR_INVALID_ARG; }
+    if (!(o->gamma0 > 0.0) || !(o->gamma_final > 0.0) || !std::isfinite(o->gamma0) || !std::isfinite(o->gamma_final)) {
+        set_error("gamma0 and gamma_final must be positive"); return DL_ERR_INVALID_ARG;
+    }
+    if (o->n_stages < 1) { set_error("n_stages must be >= 1"); return DL_ERR_INVALID_ARG; }
+    if (o->max_iters < 0 || o->check_every < 0 || o->stage_iters < 0) { set_error("negative iteration count"); return DL_ERR_INVALID_ARG; }
+    if (!(o->max_step > 0.0) || !(o->init_step > 0.0)) { set_error("steps must be positive"); return DL_ERR_INVALID_ARG; }
+    if (!(o->tol_rel_gap >= 0.0) || !(o->stage_tol >= 0.0)) { set_error("tolerances must be >= 0"); return DL_ERR_INVALID_ARG; }
+    if (o->graph_iters < 0) { set_error("graph_iters must be >= 0"); return DL_ERR_INVALID_ARG; }
+    return DL_OK;
+}
+
+SolveParams make_params(const dl_solve_opts* o)
+{
+    SolveParams P;
+    std::memset(&P, 0, sizeof P);
+    P.gamma0 = o->gamma0;
+    P.gamma_final = o->n_stages > 1 ? o->gamma_final : o->gamma0;
+    P.stage_tol = o->stage_tol;
+    P.tol = o->tol_rel_gap;
+    P.max_step = o->max_step;
+    P.init_step = o->init_step;
+    P.stage_iters = o->stage_iters;
+    P.max_iters = o->max_iters;
+    P.check_every = o->check_every;
+    P.n_stages = o->n_stages;
+    P.momentum = o->momentum;
+    P.adaptive = o->adaptive;
+    return P;
+}
+
+bool is_check_iter(const dl_solve_opts* o, int64_t k)
+{
+    return o->check_every > 0 && ((k + 1) % o->check_every == 0 || k + 1 == o->max_iters);
+}
+
+}  // namespace dlh
+
+// ---------------------------------------------------------------------------
+// dual evaluation
+// ---------------------------------------------------------------------------
+extern "C" dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, double gamma, double* grad_dev,
+                                  double* x_dev, dl_eval* eval_host, void* hip_stream)
+{
+    if (!p || !lambda_dev || !grad_dev) { set_error("NULL argument"); return DL_ERR_INVALID_ARG; }
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) { set_error("gamma must be positive and finite"); return DL_ERR_INVALID_ARG; }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int check = eval_host ? 1 : 0;
+    HIP_TRY(dl::launch_permute_in(lambda_dev, p->orig, p->J, p->lam_int, s), "permute lambda");
+    GradArgs g = dlh::grad_args(p, p->lam_int, nullptr, gamma, nullptr, x_dev);
+    HIP_TRY(launch_grad(g, p->storage, check != 0, p->has_w != 0, s), "gradient kernel");
+    ReduceArgs r = dlh::reduce_args(p, check, 1, p->lam_int, nullptr, gamma, nullptr, grad_dev);
+    HIP_TRY(launch_reduce(r, p->nblk2, s), "reduce kernel");
+    if (eval_host) {
+        HIP_TRY(launch_eval_finish(p->obj_part, p->nchunks, p->blockpart, p->nblk2, 1, gamma, p->eval6, s),
+                "evaluation kernel");
+        double h[8];
+        HIP_TRY(hipMemcpyAsync(h, p->eval6, 6 * sizeof(double), hipMemcpyDeviceToHost, s), "copy scalars");
+        HIP_TRY(hipStreamSynchronize(s), "synchronize");
+        eval_host->g = h[0];
+        eval_host->cx = h[1];
+        eval_host->reg = h[2];
+        eval_host->P = h[3];
+        eval_host->rel_gap = h[4];
+        eval_host->max_infeas = h[5];
+    }
+    return DL_OK;
+}
+
+extern "C" dl_status dl_time_grad_kernel(dl_problem* p, const double* lambda_dev, double gamma, int32_t iters,
+                                         int32_t check, double* ms_per_launch, void* hip_stream)
+{
+    if (!p || !lambda_dev || !ms_per_launch || iters < 1) { set_error("invalid argument"); return DL_ERR_INVALID_ARG; }
+    if (!(gamma > 0.0)) { set_error("gamma must be positive"); return DL_ERR_INVALID_ARG; }
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(dl::launch_permute_in(lambda_dev, p->orig, p->J, p->lam_int, s), "permute lambda");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    float tot = 0.0f;
+    dl_status st = DL_OK;
+    for (int i = 0; i < iters && st == DL_OK; ++i) {
+        GradArgs g = dlh::grad_args(p, p->lam_int, nullptr, gamma, nullptr, nullptr);
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_grad(g, p->storage, check != 0, p->has_w != 0, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        ReduceArgs r = dlh::reduce_args(p, check, 1, p->lam_int, nullptr, gamma, nullptr, p->lam);
+        if (e == hipSuccess) e = launch_reduce(r, p->nblk2, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) st = hip_fail(e, "timing");
+        tot += ms;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == DL_OK) *ms_per_launch = tot / iters;
+    return st;
+}

@@ -1,0 +1,77 @@
+// Internal layout shared by the host code and the HIP kernels of libdualip.
+//
+// Device layout of one problem (built once by dl_problem_create):
+//
+//   Edge stream.  Every primal variable (edge e = (source i, destination j))
+//   sits at one stream position holding a_e, c_e (storage type), dst_e (int32,
+//   destination after relabelling), and when needed u_e (box bound, f32),
+//   iv_e = 1/v_e^2 (primal scale, f32) and perm_e (original column, int64,
+//   only read when x is requested).
+//
+//   Work items.  Blocks are grouped by projection type and degree d:
+//     LANE  d <= 16 (8 for FP64 storage): groups of up to 64 blocks of one
+//           exact degree; lane l of a
+//           wave owns block l of the group, whose k-th edge is stored at
+//           base + k*nb + l, so every load of the wave is one contiguous
+//           nb-element run (coalesced) and the whole projection runs in the
+//           lane's registers.
+//     WAVE  up to d <= 512: one wave per block, edge k at base + k.
+//     WG    d > 512: one workgroup per block, edge k at base + k.
+//
+//   Chunks.  The workgroups of the fused gradient kernel each take one
+//   chunk: a range of LANE/WAVE items (spread over the chunk's waves) and a
+//   range of WG items, balanced by nonzeros.  Each chunk owns one row of the
+//   per-destination partial-sum buffer, so results do not depend on timing.
+//
+//   Destinations.  Relabelled by descending degree; the first K (lds_rows)
+//   live in LDS during the gradient pass (lam in FP64 and f32 partial sums),
+//   the rest read lam from global memory and add to FP64 global accumulators.
+#pragma once
+#include <stdint.h>
+
+namespace dl {
+
+constexpr int kWG = 512;                // threads of a gradient workgroup
+constexpr int kWaves = kWG / 64;
+constexpr int kLaneMaxDeg = 16;         // LANE items (registers: 16 edges per lane)
+constexpr int kLaneMaxDegF64 = 8;       // LANE items with FP64 storage
+constexpr int kWaveMaxDeg = 512;        // WAVE items (8 edges per lane)
+
+enum ItemKind : uint8_t { ITEM_LANE = 0, ITEM_WAVE = 1, ITEM_WG = 2 };
+
+struct Item {                // 16 bytes
+    int64_t base;            // first stream position
+    int32_t d;               // degree (edges per block)
+    uint16_t nb;             // blocks in the group (LANE), 1 otherwise
+    uint8_t kind;            // ItemKind
+    uint8_t proj;            // dl_proj
+};
+static_assert(sizeof(Item) == 16, "Item layout");
+
+struct Chunk {               // wave items [a0, a1), workgroup items [b0, b1)
+    int32_t a0, a1, b0, b1;
+};
+
+// Scalars of the iteration that live on the device (one per solve slot).
+struct SolveState {
+    double gamma, eta, eta_cap, tm;
+    double g, P, rel_gap, max_infeas, gnorm, obj;
+    double gamma_eval;       // gamma of the last evaluation
+    int64_t k, ks;
+    int32_t stage, done, converged, status;
+    int32_t stage_eval, pad;
+};
+
+// Constant parameters of a solve (kernel argument).
+struct SolveParams {
+    double gamma0, gamma_final, stage_tol, tol, max_step, init_step;
+    int64_t stage_iters, max_iters, check_every;
+    int32_t n_stages, momentum, adaptive, pad;
+};
+
+// Number of per-block FP64 sums written by the reduction kernel.
+constexpr int kRedStride = 8;
+// 0: sum lam_j b_j   1: |G'|^2   2: |G'-G'_prev|^2   3: |y'-y'_prev|^2
+// 4: gap correction sum_j (s_j-1) C_j + gamma/2 (s_j^2-1) Q_j   5: max infeasibility
+
+}  // namespace dl

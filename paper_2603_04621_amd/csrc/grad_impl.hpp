@@ -1,0 +1,757 @@
+// Device code of the fused dual-gradient kernel (included once per storage
+// type by grad_f64.hip, grad_f32.hip and grad_bf16.hip).
+//
+// One pass over the edge stream per dual-gradient evaluation (Section 3.1,
+// Danskin): gather lam for each edge's destination, t_e = -(c_e + a_e
+// lam_j(e)) in FP64, project each source block onto its simple set (Eq.(4),(5)
+// simplex or box), and accumulate a_e x_e into the per-destination sums of
+// A x.  Nothing per-edge is written back.  The work is sparse and
+// bandwidth-bound, so it runs on the vector ALUs; no MFMA.
+//
+// Simplex threshold.  With w_e = 1/(gamma v_e^2) the block solution is
+// x_e = max(0, w_e (t_e - tau)), tau = 0 when sum_e max(0, w_e t_e) <= 1, else
+// the root of sum_e max(0, w_e (t_e - tau)) = 1.  Since x_e <= 1 forces
+// tau >= t_e - 1/w_e, the search starts at tau_0 = max(0, max_e (t_e - 1/w_e)),
+// whose set S_0 = {t > tau_0} holds every active edge.  Then the fixed point
+// tau <- (sum_S w t - 1) / sum_S w with S = {t > tau} (Michelot 1986) rises
+// monotonically and stops when S no longer shrinks; the result is exact (KKT
+// hold for the final set), not limited by a bisection tolerance.  Because
+// tau_1 > tau_0 (the top edge alone already gives w (t - tau_0) = 1) every
+// set along the way is a threshold set {t > tau}, so no membership mask is
+// kept.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dl {
+
+// ---------------------------------------------------------------------------
+// stored value types
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct Val;
+template <>
+struct Val<double> {
+    using reg = double;
+    static __device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ double cvt(double v) { return v; }
+};
+template <>
+struct Val<float> {
+    using reg = float;
+    static __device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ float cvt(float v) { return v; }
+};
+template <>
+struct Val<uint16_t> {   // bfloat16 bits: widen by a 16-bit shift (exact)
+    using reg = float;
+    static __device__ __forceinline__ float ld(const uint16_t* p, int64_t i)
+    {
+        return __uint_as_float(((uint32_t)p[i]) << 16);
+    }
+    static __device__ __forceinline__ float cvt(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+};
+
+// an opaque copy: keeps the compiler from carrying an FP64 widening of a
+// stored value from one pass to the next (it would double its registers)
+__device__ __forceinline__ float opq(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ double opq(double v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// load at a 32-bit unsigned byte offset from a wave-uniform base: lets the
+// compiler use the scalar-base + 32-bit vector-offset form of global loads
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t elem)
+{
+    return *(const T*)((const char*)base + elem * (uint32_t)sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// wave / workgroup reductions (butterfly: every lane ends with the same bits)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// wave-uniform copies (scalar registers) of values the compiler cannot prove uniform
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+struct Lds {
+    __amdgpu_buffer_rsrc_t lam_rsrc;   // global lam (rows beyond K)
+    double* red;   // [4 * kWaves] workgroup reduction scratch
+    double* lam;   // [K] (normal passes)
+    float* hg;     // [K] sum a x
+    float* hc;     // [K] sum c x   (check passes)
+    float* hq;     // [K] sum v^2 x^2 (check passes)
+};
+
+// three sums and a count over the whole workgroup (all threads call it)
+__device__ __forceinline__ void wg_sum3(double& a, double& b, int& n, double* red)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    n = wave_sum_i(n);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = a;
+        red[kWaves + w] = b;
+        red[2 * kWaves + w] = (double)n;
+    }
+    __syncthreads();
+    a = 0.0;
+    b = 0.0;
+    double nn = 0.0;
+    for (int i = 0; i < kWaves; ++i) {
+        a += red[i];
+        b += red[kWaves + i];
+        nn += red[2 * kWaves + i];
+    }
+    n = (int)nn;
+}
+__device__ __forceinline__ void wg_sum_max(double& s, double& m, double* red)
+{
+    s = wave_sum(s);
+    m = wave_max(m);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = s;
+        red[kWaves + w] = m;
+    }
+    __syncthreads();
+    s = 0.0;
+    m = -INFINITY;
+    for (int i = 0; i < kWaves; ++i) {
+        s += red[i];
+        m = fmax(m, red[kWaves + i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-edge helpers
+// ---------------------------------------------------------------------------
+// lam of row j: from LDS for rows below K; rows beyond K come from a raw
+// buffer load whose offset is pushed out of range (returns 0, no memory
+// access) for LDS rows, so no per-edge branch or flat load is needed.  Check
+// passes keep the LDS for the three sums and read lam from global memory.
+template <bool CHECK, bool TAIL>
+__device__ __forceinline__ double get_lam(const Lds& s, const GradArgs& g, int j)
+{
+    if (CHECK) return ldo(g.lam, (uint32_t)j);
+    if (!TAIL) return s.lam[j];
+    const double l = s.lam[j < g.K ? j : g.K - 1];
+    const uint32_t off = j >= g.K ? (uint32_t)j * 8u : 0xFFFFFFFFu;
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(s.lam_rsrc, off, 0, 0);
+    const double gv = __longlong_as_double((long long)(((unsigned long long)v.y << 32) | v.x));
+    return j < g.K ? l : gv;
+}
+
+__device__ __forceinline__ void lds_add(float* p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void gl_add(double* p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// per-destination sums: rows below K in LDS (f32), the rest in FP64 global
+// accumulators (a separate, rarely taken path so the main loop stays lean)
+template <bool CHECK>
+__device__ __forceinline__ void accum_lds(const Lds& s, int j, double ax, double cx, double q)
+{
+    lds_add(&s.hg[j], (float)ax);
+    if (CHECK) {
+        lds_add(&s.hc[j], (float)cx);
+        lds_add(&s.hq[j], (float)q);
+    }
+}
+template <bool CHECK>
+__device__ __forceinline__ void accum_tail(const GradArgs& g, int j, double ax, double cx, double q)
+{
+    gl_add(&g.tail[j], ax);
+    if (CHECK) {
+        gl_add(&g.tail[g.J + j], cx);
+        gl_add(&g.tail[2 * (int64_t)g.J + j], q);
+    }
+}
+template <bool CHECK, bool TAIL>
+__device__ __forceinline__ void accum(const Lds& s, const GradArgs& g, int j, double ax, double cx,
+                                      double q)
+{
+    if (!TAIL || j < g.K) accum_lds<CHECK>(s, j, ax, cx, q);
+    else accum_tail<CHECK>(g, j, ax, cx, q);
+}
+
+// the projected value of one edge given its block threshold
+template <bool BOX>
+__device__ __forceinline__ double xval(double t, double w, double tau, float u)
+{
+    if (BOX) {
+        const double z = w * t;
+        return z > 0.0 ? (z < (double)u ? z : (double)u) : 0.0;
+    }
+    const double z = w * (t - tau);
+    return z > 0.0 ? z : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Objective bookkeeping.  With t = -(c + A'lam) the dual objective is
+//   g = c'x + gamma/2 |D_v x|^2 + lam'(A x - b) = -t'x + gamma/2 |D_v x|^2 - lam'b,
+// so ordinary passes accumulate ot = sum t x and oq = sum v^2 x^2 only (c is
+// not kept past pass 1); check passes also accumulate oc = sum c x for the
+// primal value of the gap.
+// ---------------------------------------------------------------------------
+struct Obj {
+    double ot, oq, oc;
+};
+
+// ---------------------------------------------------------------------------
+// LANE items: one lane per block, the block's d <= P values in registers
+// ---------------------------------------------------------------------------
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+__device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, const Lds& s,
+                                           double gamma, Obj& ob)
+{
+    static_assert(P <= 16, "lane blocks hold at most 16 edges");
+    using R = typename Val<VT>::reg;
+    const int lane = threadIdx.x & 63;
+    const int d = uni(it.d), nb = uni(it.nb);
+    const int64_t ib = uni64(it.base);
+    const bool act = lane < nb;
+    // idle lanes read the last block's addresses (same lines, no extra traffic);
+    // per-lane offsets are 32-bit from a wave-uniform base
+    const int lc = act ? lane : nb - 1;
+    const VT* __restrict__ A = (const VT*)g.A + ib;
+    const VT* __restrict__ C = (const VT*)g.C + ib;
+    const int32_t* __restrict__ Dst = g.dst + ib;
+    const float* __restrict__ U = BOX ? g.U + ib : nullptr;
+    const float* __restrict__ IV = HASW ? g.IV + ib : nullptr;
+    const double inv_g = 1.0 / gamma;
+
+    double t[P];
+    R av[P];
+    R cv[CHECK ? P : 1];
+    int jv[P];
+    float uv[BOX ? P : 1];
+    float iv[HASW ? P : 1];
+
+    // pass 1: loads (rows beyond d re-read row d-1, so every load is
+    // unconditional and the wave issues them back to back), t in FP64
+    // (in tiles of 8 rows with a scheduling fence between them, which caps the
+    // registers the compiler spends on loads in flight)
+    constexpr int T = P < 8 ? P : 8;
+#pragma unroll
+    for (int k0 = 0; k0 < P; k0 += T) {
+#pragma unroll
+        for (int k = k0; k < k0 + T; ++k) {
+            const int kk = k < d ? k : d - 1;
+            const uint32_t off = (uint32_t)(lc + kk * nb);
+            av[k] = Val<VT>::cvt(ldo(A, off));
+            const R c = Val<VT>::cvt(ldo(C, off));
+            jv[k] = ldo(Dst, off);
+            if (BOX) uv[k] = ldo(U, off);
+            if (HASW) iv[k] = ldo(IV, off);
+            const double lam = get_lam<CHECK, TAIL>(s, g, jv[k]);
+            const double tk = -((double)c + (double)av[k] * lam);
+            t[k] = (k < d && act) ? tk : -INFINITY;
+            if (CHECK) cv[k] = c;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // pass 2: simplex threshold in registers
+    double tau = 0.0;
+    if (!BOX) {
+        double s0 = 0.0, mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+            const double iw = HASW ? gamma / (double)iv[k] : gamma;
+            const double z = w * t[k];
+            s0 += z > 0.0 ? z : 0.0;
+            const double lo = t[k] - iw;
+            mx = lo > mx ? lo : mx;
+        }
+        if (s0 > 1.0) {
+            tau = mx > 0.0 ? mx : 0.0;
+            double sw = 0.0, swt = 0.0;
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                const bool in = t[k] > tau;
+                sw += in ? w : 0.0;
+                swt += in ? w * t[k] : 0.0;
+                n += in ? 1 : 0;
+            }
+            for (int rep = 0; rep < 2 * P + 4; ++rep) {
+                const double tn = (swt - 1.0) / sw;
+                double sw2 = 0.0, swt2 = 0.0;
+                int n2 = 0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                    const bool in = t[k] > tn;
+                    sw2 += in ? w : 0.0;
+                    swt2 += in ? w * t[k] : 0.0;
+                    n2 += in ? 1 : 0;
+                }
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                sw = sw2;
+                swt = swt2;
+                n = n2;
+            }
+        }
+    }
+
+    // pass 3: x, objective, per-destination sums of the LDS-resident rows
+    bool tail = false;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        if (k < d) {
+            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+            const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+            if (x != 0.0) {
+                const double q2 = HASW ? x * x / (double)iv[k] : x * x;
+                ob.ot += t[k] * x;
+                ob.oq += q2;
+                const double cx = CHECK ? (double)cv[k] * x : 0.0;
+                if (CHECK) ob.oc += cx;
+                if (!TAIL || jv[k] < g.K) accum_lds<CHECK>(s, jv[k], (double)opq(av[k]) * x, cx, q2);
+                else tail = true;
+            }
+        }
+    }
+    // rows beyond K (only when some lane of the wave has one)
+    if (TAIL && __builtin_amdgcn_ballot_w64(tail)) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k < d) {
+                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+                if (x != 0.0 && jv[k] >= g.K) {
+                    const double q2 = HASW ? x * x / (double)iv[k] : x * x;
+                    accum_tail<CHECK>(g, jv[k], (double)opq(av[k]) * x, CHECK ? (double)opq(cv[k]) * x : 0.0, q2);
+                }
+            }
+        }
+    }
+    if (g.X) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k < d && act) {
+                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                g.X[g.perm[ib + lc + k * nb]] = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// WAVE items: one wave per block, edge e = lane + 64 k, k < P2
+// ---------------------------------------------------------------------------
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P2>
+__device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, const Lds& s,
+                                           double gamma, Obj& ob)
+{
+    using R = typename Val<VT>::reg;
+    const int lane = threadIdx.x & 63;
+    const int d = uni(it.d);
+    const int64_t ib = uni64(it.base);
+    const VT* __restrict__ A = (const VT*)g.A + ib;
+    const VT* __restrict__ C = (const VT*)g.C + ib;
+    const int32_t* __restrict__ Dst = g.dst + ib;
+    const double inv_g = 1.0 / gamma;
+    double t[P2];
+    R av[P2];
+    R cv[CHECK ? P2 : 1];
+    int jv[P2];
+    float uv[BOX ? P2 : 1];
+    float iv[HASW ? P2 : 1];
+#pragma unroll
+    for (int k = 0; k < P2; ++k) {
+        const int e = lane + 64 * k;
+        const uint32_t ee = (uint32_t)(e < d ? e : d - 1);
+        av[k] = Val<VT>::cvt(ldo(A, ee));
+        const R c = Val<VT>::cvt(ldo(C, ee));
+        jv[k] = ldo(Dst, ee);
+        if (BOX) uv[k] = ldo(g.U + ib, ee);
+        if (HASW) iv[k] = ldo(g.IV + ib, ee);
+        const double lam = get_lam<CHECK, TAIL>(s, g, jv[k]);
+        const double tk = -((double)c + (double)av[k] * lam);
+        t[k] = e < d ? tk : -INFINITY;
+        if (CHECK) cv[k] = c;
+    }
+    double tau = 0.0;
+    if (!BOX) {
+        double s0 = 0.0, mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < P2; ++k) {
+            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+            const double iw = HASW ? gamma / (double)iv[k] : gamma;
+            const double z = w * t[k];
+            s0 += z > 0.0 ? z : 0.0;
+            mx = fmax(mx, t[k] - iw);
+        }
+        s0 = wave_sum(s0);
+        mx = wave_max(mx);
+        if (s0 > 1.0) {
+            tau = mx > 0.0 ? mx : 0.0;
+            double sw = 0.0, swt = 0.0;
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < P2; ++k) {
+                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                const bool in = t[k] > tau;
+                sw += in ? w : 0.0;
+                swt += in ? w * t[k] : 0.0;
+                n += in ? 1 : 0;
+            }
+            sw = wave_sum(sw);
+            swt = wave_sum(swt);
+            n = wave_sum_i(n);
+            for (int rep = 0; rep < 2 * 64 * P2 + 4; ++rep) {
+                const double tn = (swt - 1.0) / sw;
+                double sw2 = 0.0, swt2 = 0.0;
+                int n2 = 0;
+#pragma unroll
+                for (int k = 0; k < P2; ++k) {
+                    const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                    const bool in = t[k] > tn;
+                    sw2 += in ? w : 0.0;
+                    swt2 += in ? w * t[k] : 0.0;
+                    n2 += in ? 1 : 0;
+                }
+                sw2 = wave_sum(sw2);
+                swt2 = wave_sum(swt2);
+                n2 = wave_sum_i(n2);
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                sw = sw2;
+                swt = swt2;
+                n = n2;
+            }
+        }
+    }
+    bool tail = false;
+#pragma unroll
+    for (int k = 0; k < P2; ++k) {
+        const int e = lane + 64 * k;
+        if (e < d) {
+            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+            const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+            if (x != 0.0) {
+                const double q2 = HASW ? x * x / (double)iv[k] : x * x;
+                ob.ot += t[k] * x;
+                ob.oq += q2;
+                const double cx = CHECK ? (double)cv[k] * x : 0.0;
+                if (CHECK) ob.oc += cx;
+                if (!TAIL || jv[k] < g.K) accum_lds<CHECK>(s, jv[k], (double)opq(av[k]) * x, cx, q2);
+                else tail = true;
+            }
+        }
+    }
+    if (TAIL && __builtin_amdgcn_ballot_w64(tail)) {
+#pragma unroll
+        for (int k = 0; k < P2; ++k) {
+            const int e = lane + 64 * k;
+            if (e < d) {
+                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+                if (x != 0.0 && jv[k] >= g.K) {
+                    const double q2 = HASW ? x * x / (double)iv[k] : x * x;
+                    accum_tail<CHECK>(g, jv[k], (double)opq(av[k]) * x, CHECK ? (double)opq(cv[k]) * x : 0.0, q2);
+                }
+            }
+        }
+    }
+    if (g.X) {
+#pragma unroll
+        for (int k = 0; k < P2; ++k) {
+            const int e = lane + 64 * k;
+            if (e < d) {
+                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                g.X[g.perm[ib + e]] = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// WG items: one workgroup per block of any degree; t is recomputed on every
+// pass (the block's data stays in L2 between passes)
+// ---------------------------------------------------------------------------
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+__device__ __forceinline__ double edge_t(const GradArgs& g, const Lds& s, int64_t idx, double& w,
+                                         double inv_g)
+{
+    const VT* __restrict__ A = (const VT*)g.A;
+    const VT* __restrict__ C = (const VT*)g.C;
+    const double a = (double)Val<VT>::ld(A, idx);
+    const double c = (double)Val<VT>::ld(C, idx);
+    const int j = g.dst[idx];
+    w = HASW ? (double)g.IV[idx] * inv_g : inv_g;
+    return -(c + a * get_lam<CHECK, TAIL>(s, g, j));
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+__device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, const Lds& s, double gamma, Obj& ob)
+{
+    const int d = uni(it.d);
+    const int64_t base = uni64(it.base);
+    const double inv_g = 1.0 / gamma;
+    double tau = 0.0;
+    if (!BOX) {
+        double s0 = 0.0, mx = -INFINITY;
+        for (int e = threadIdx.x; e < d; e += kWG) {
+            double w;
+            const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+            const double z = w * t;
+            s0 += z > 0.0 ? z : 0.0;
+            mx = fmax(mx, t - 1.0 / w);
+        }
+        wg_sum_max(s0, mx, s.red);
+        if (s0 > 1.0) {
+            tau = mx > 0.0 ? mx : 0.0;
+            double sw = 0.0, swt = 0.0;
+            int n = 0;
+            for (int e = threadIdx.x; e < d; e += kWG) {
+                double w;
+                const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+                if (t > tau) {
+                    sw += w;
+                    swt += w * t;
+                    ++n;
+                }
+            }
+            wg_sum3(sw, swt, n, s.red);
+            for (int rep = 0; rep < 2 * d + 4; ++rep) {
+                const double tn = (swt - 1.0) / sw;
+                double sw2 = 0.0, swt2 = 0.0;
+                int n2 = 0;
+                for (int e = threadIdx.x; e < d; e += kWG) {
+                    double w;
+                    const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+                    if (t > tn) {
+                        sw2 += w;
+                        swt2 += w * t;
+                        ++n2;
+                    }
+                }
+                wg_sum3(sw2, swt2, n2, s.red);
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                sw = sw2;
+                swt = swt2;
+                n = n2;
+            }
+        }
+    }
+    const VT* __restrict__ A = (const VT*)g.A;
+    const VT* __restrict__ C = (const VT*)g.C;
+    for (int e = threadIdx.x; e < d; e += kWG) {
+        const int64_t idx = base + e;
+        double w;
+        const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, idx, w, inv_g);
+        const double x = xval<BOX>(t, w, tau, BOX ? g.U[idx] : 0.0f);
+        if (x != 0.0) {
+            const double a = (double)Val<VT>::ld(A, idx);
+            const double q2 = HASW ? x * x / (double)g.IV[idx] : x * x;
+            ob.ot += t * x;
+            ob.oq += q2;
+            const double cx = CHECK ? (double)Val<VT>::ld(C, idx) * x : 0.0;
+            if (CHECK) ob.oc += cx;
+            accum<CHECK, TAIL>(s, g, g.dst[idx], a * x, cx, q2);
+        }
+        if (g.X) g.X[g.perm[idx]] = x;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// the fused gradient kernel: one workgroup per chunk
+// ---------------------------------------------------------------------------
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+__device__ __forceinline__ void lane_dispatch(const GradArgs& g, const Item& it, const Lds& s,
+                                              double gamma, Obj& ob)
+{
+    const int d = it.d;
+    if (d <= 4) lane_group<VT, CHECK, HASW, TAIL, BOX, 4>(g, it, s, gamma, ob);
+    else if (d <= 8 || sizeof(VT) == 8) lane_group<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
+    else if (d <= 12) lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 12>(g, it, s, gamma, ob);
+    else lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 16>(g, it, s, gamma, ob);
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+__device__ __forceinline__ void wave_dispatch(const GradArgs& g, const Item& it, const Lds& s,
+                                              double gamma, Obj& ob)
+{
+    const int d = it.d;
+    if (d <= 64) wave_block<VT, CHECK, HASW, TAIL, BOX, 1>(g, it, s, gamma, ob);
+    else if (d <= 128) wave_block<VT, CHECK, HASW, TAIL, BOX, 2>(g, it, s, gamma, ob);
+    else if (d <= 256) wave_block<VT, CHECK, HASW, TAIL, BOX, 4>(g, it, s, gamma, ob);
+    else wave_block<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+__global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
+{
+    if (g.done && *g.done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds s;
+    s.lam_rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g.lam, (short)0, g.J * 8, 0x00020000);
+    s.red = (double*)smem;
+    unsigned char* p = smem + 4 * kWaves * sizeof(double);
+    const int K = g.K;
+    s.lam = nullptr;
+    if (!CHECK) {
+        s.lam = (double*)p;
+        p += (size_t)K * sizeof(double);
+    }
+    s.hg = (float*)p;
+    p += (size_t)K * sizeof(float);
+    s.hc = s.hq = nullptr;
+    if (CHECK) {
+        s.hc = (float*)p;
+        p += (size_t)K * sizeof(float);
+        s.hq = (float*)p;
+    }
+    const double gamma = g.gamma_ptr ? *g.gamma_ptr : g.gamma_val;
+    for (int j = threadIdx.x; j < K; j += kWG) {
+        if (!CHECK) s.lam[j] = g.lam[j];
+        s.hg[j] = 0.0f;
+        if (CHECK) {
+            s.hc[j] = 0.0f;
+            s.hq[j] = 0.0f;
+        }
+    }
+    __syncthreads();
+
+    const Chunk ch = g.chunks[blockIdx.x];
+    Obj ob = {0.0, 0.0, 0.0};
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int i = ch.a0 + wave; i < ch.a1; i += kWaves) {
+        const Item it = g.items[i];
+        if (it.kind == ITEM_LANE) {
+            if (it.proj == 1) lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
+            else lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+        } else {
+            if (it.proj == 1) wave_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
+            else wave_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+        }
+    }
+    for (int i = ch.b0; i < ch.b1; ++i) {
+        const Item it = g.items[i];
+        if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
+        else wg_block<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+    }
+    __syncthreads();
+
+    // flush: this chunk's row of partial sums, and its objective part
+    const int64_t plane = (int64_t)g.nchunks * K;
+    float* row = g.part + (int64_t)blockIdx.x * K;
+    for (int j = threadIdx.x; j < K; j += kWG) {
+        row[j] = s.hg[j];
+        if (CHECK) {
+            row[plane + j] = s.hc[j];
+            row[2 * plane + j] = s.hq[j];
+        }
+    }
+    ob.ot = wave_sum(ob.ot);
+    ob.oq = wave_sum(ob.oq);
+    ob.oc = wave_sum(ob.oc);
+    if ((threadIdx.x & 63) == 0) {
+        s.red[threadIdx.x >> 6] = ob.ot;
+        s.red[kWaves + (threadIdx.x >> 6)] = ob.oq;
+        s.red[2 * kWaves + (threadIdx.x >> 6)] = ob.oc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int i = 0; i < kWaves; ++i) {
+            a += s.red[i];
+            b += s.red[kWaves + i];
+            c += s.red[2 * kWaves + i];
+        }
+        g.obj_part[3 * blockIdx.x] = a;
+        g.obj_part[3 * blockIdx.x + 1] = b;
+        g.obj_part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+static hipError_t launch_grad_t(const GradArgs& a, hipStream_t s)
+{
+    const size_t lds = grad_lds_bytes(a.K, CHECK);
+    hipLaunchKernelGGL((grad_kernel<VT, CHECK, HASW, TAIL>), dim3(a.nchunks), dim3(kWG), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s)
+{
+    const bool tail = a.K < a.J;
+#define DL_L(C, W, T) if (check == C && has_w == W && tail == T) return launch_grad_t<VT, C, W, T>(a, s);
+    DL_L(false, false, false) DL_L(false, false, true) DL_L(false, true, false) DL_L(false, true, true)
+    DL_L(true, false, false) DL_L(true, false, true) DL_L(true, true, false) DL_L(true, true, true)
+#undef DL_L
+    return hipErrorInvalidValue;
+}
+
+template <typename VT>
+hipError_t set_grad_attributes_vt(size_t lds)
+{
+    hipError_t e = hipSuccess, r;
+#define DL_A(C, W, T)                                                                        \
+    r = hipFuncSetAttribute((const void*)grad_kernel<VT, C, W, T>,                          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+    if (r != hipSuccess) e = r;
+    DL_A(false, false, false) DL_A(false, false, true) DL_A(false, true, false) DL_A(false, true, true)
+    DL_A(true, false, false) DL_A(true, false, true) DL_A(true, true, false) DL_A(true, true, true)
+#undef DL_A
+    return e;
+}
+
+#define DL_INSTANTIATE_GRAD(VT)                                                              \
+    template hipError_t launch_grad_vt<VT>(const GradArgs&, bool, bool, hipStream_t);     \
+    template hipError_t set_grad_attributes_vt<VT>(size_t);
+
+
+}  // namespace dl

@@ -1,0 +1,443 @@
+// HIP kernels of libdualip for CDNA4 (gfx950): the per-destination reduction,
+// the ascent step and small helpers.  The fused gradient kernel lives in
+// grad_impl.hpp (instantiated per storage type).
+//
+// The hot path is one fused pass over the edge stream per dual-gradient
+// evaluation (Section 3.1, Danskin): gather lam for each edge's destination,
+// t_e = -(c_e + a_e lam_j(e)) in FP64, project each source block onto its
+// simple set (Eq.(4),(5) simplex or box), and accumulate a_e x_e into the
+// per-destination sums of A x.  Nothing per-edge is written back.  The work is
+// sparse and bandwidth-bound, so it runs on the vector ALUs; no MFMA.
+//
+// Simplex threshold.  With w_e = 1/(gamma v_e^2) the block solution is
+// x_e = max(0, w_e (t_e - tau)), tau = 0 when sum_e max(0, w_e t_e) <= 1, else
+// the root of sum_e max(0, w_e (t_e - tau)) = 1.  Since x_e <= 1 forces
+// tau >= t_e - 1/w_e, the search starts at tau_0 = max(0, max_e (t_e - 1/w_e)),
+// whose set S_0 = {t > tau_0} holds every active edge.  Then the fixed point
+// tau <- (sum_S w t - 1) / sum_S w with S = {t > tau} (Michelot 1986) rises
+// monotonically and stops when S no longer shrinks; the result is exact (KKT
+// hold for the final set), not limited by a bisection tolerance.  Because
+// tau_1 > tau_0 (the top edge alone already gives w (t - tau_0) = 1) every
+// set along the way is a threshold set {t > tau}, so no membership mask is
+// kept.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dl {
+
+// ---------------------------------------------------------------------------
+// shared helpers (the gradient kernel has its own copies in grad_impl.hpp)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <typename VT>
+hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s);
+template <typename VT>
+hipError_t set_grad_attributes_vt(size_t lds);
+
+size_t grad_lds_bytes(int K, bool check)
+{
+    return 4 * kWaves * sizeof(double) + (size_t)K * (check ? 3 * sizeof(float)
+                                                            : sizeof(double) + sizeof(float));
+}
+
+hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s)
+{
+    if (a.nchunks <= 0) return hipSuccess;
+    switch (storage) {
+    case 0: return launch_grad_vt<double>(a, check, has_w, s);
+    case 1: return launch_grad_vt<float>(a, check, has_w, s);
+    default: return launch_grad_vt<uint16_t>(a, check, has_w, s);
+    }
+}
+
+hipError_t set_grad_attributes(size_t lds)
+{
+    hipError_t e = hipSuccess, r;
+    if ((r = set_grad_attributes_vt<double>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<float>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<uint16_t>(lds)) != hipSuccess) e = r;
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// per-destination combination of the chunk partials (fixed order)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r)
+{
+    if (r.done && *r.done) return;
+    __shared__ double sh[3][4][64];
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int j = blockIdx.x * 64 + l;
+    const int planes = r.check ? 3 : 1;
+    const int64_t plane = (int64_t)r.nchunks * r.K;
+    for (int p = 0; p < planes; ++p) {
+        double acc = 0.0;
+        if (j < r.K) {
+            const int c0 = (int)(((int64_t)r.nchunks * q) / 4);
+            const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / 4);
+            const float* col = r.part + p * plane + j;
+            int c = c0;
+            for (; c + 8 <= c1; c += 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)(c + u) * r.K];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += (double)v[u];
+            }
+            for (; c < c1; ++c) acc += (double)col[(int64_t)c * r.K];
+        }
+        sh[p][q][l] = acc;
+    }
+    __syncthreads();
+    if (q != 0) return;
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (j < r.J) {
+        const double gamma = r.gamma_ptr ? *r.gamma_ptr : r.gamma_val;
+        double ax, cj = 0.0, qj = 0.0;
+        if (j < r.K) {
+            ax = ((sh[0][0][l] + sh[0][1][l]) + sh[0][2][l]) + sh[0][3][l];
+            if (r.check) {
+                cj = ((sh[1][0][l] + sh[1][1][l]) + sh[1][2][l]) + sh[1][3][l];
+                qj = ((sh[2][0][l] + sh[2][1][l]) + sh[2][2][l]) + sh[2][3][l];
+            }
+        } else {
+            ax = r.tail[j];
+            r.tail[j] = 0.0;
+            cj = r.tail[r.J + j];
+            qj = r.tail[2 * (int64_t)r.J + j];
+            r.tail[r.J + j] = 0.0;
+            r.tail[2 * (int64_t)r.J + j] = 0.0;
+        }
+        const double bj = r.b[j];
+        const double res = ax - bj;
+        S[0] = r.lam[j] * bj;
+        if (r.mode == 1) {
+            r.grad_out[r.orig[j]] = res;
+        } else {
+            const double Gj = r.D[j] * res;
+            r.G[j] = Gj;
+            S[1] = Gj * Gj;
+            const double dg = Gj - r.Gp[j];
+            S[2] = dg * dg;
+            const double dy = r.y[j] - r.yp[j];
+            S[3] = dy * dy;
+        }
+        if (r.check) {
+            const double sj = ax > bj ? bj / ax : 1.0;
+            S[4] = (sj - 1.0) * cj + 0.5 * gamma * (sj * sj - 1.0) * qj;
+            S[5] = res > 0.0 ? res : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) S[i] = wave_sum(S[i]);
+    S[5] = wave_max(S[5]);
+    if (l == 0) {
+        double* out = r.blockpart + (int64_t)blockIdx.x * kRedStride;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) out[i] = S[i];
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(nblk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// deterministic block reduction of the scalars (all threads of one WG)
+// ---------------------------------------------------------------------------
+// the scalar kernels run one workgroup of kScalarThreads threads
+constexpr int kScalarThreads = 1024;
+constexpr int kSW = kScalarThreads / 64;
+
+__device__ __forceinline__ void reduce_scalars(const double* obj_part, int nchunks, const double* bp,
+                                               int nblk, double* out /*[9] shared*/,
+                                               double* red /*[9*kSW] shared*/)
+{
+    // out: 0 sum t x, 1 sum v^2 x^2, 2 sum c x, 3..7 block sums 0..4, 8 max of block value 5
+    double v[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nchunks; i += blockDim.x) {
+        v[0] += obj_part[3 * i];
+        v[1] += obj_part[3 * i + 1];
+        v[2] += obj_part[3 * i + 2];
+    }
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[3 + k] += bp[(int64_t)i * kRedStride + k];
+        v[8] = fmax(v[8], bp[(int64_t)i * kRedStride + 5]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = wave_sum(v[k]);
+    v[8] = wave_max(v[8]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 9; ++k) red[k * kSW + w] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 9; ++k) {
+            double a = 0.0;
+            for (int i = 0; i < kSW; ++i) a = k == 8 ? fmax(a, red[k * kSW + i]) : a + red[k * kSW + i];
+            out[k] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// evaluation scalars: g, c'x, gamma/2 |D_v x|^2, P, rel_gap, max_infeas
+__global__ __launch_bounds__(kScalarThreads) void eval_finish_kernel(const double* obj_part, int nchunks,
+                                                                     const double* bp, int nblk, int check,
+                                                                     double gamma, double* out6)
+{
+    __shared__ double red[9 * kSW];
+    __shared__ double v[9];
+    reduce_scalars(obj_part, nchunks, bp, nblk, v, red);
+    if (threadIdx.x == 0) {
+        const double reg = 0.5 * gamma * v[1];
+        const double g = -v[0] + reg - v[3];
+        out6[0] = g;
+        out6[1] = check ? v[2] : NAN;
+        out6[2] = reg;
+        double P = NAN, rel = NAN;
+        if (check) {
+            P = v[2] + reg + v[7];
+            rel = (P - g) / fmax(1.0, fabs(g));
+        }
+        out6[3] = P;
+        out6[4] = rel;
+        out6[5] = check ? v[8] : NAN;
+    }
+}
+
+hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double* blockpart, int nblk,
+                              int check, double gamma, double* out6, hipStream_t s)
+{
+    hipLaunchKernelGGL(eval_finish_kernel, dim3(1), dim3(kScalarThreads), 0, s, obj_part, nchunks, blockpart,
+                       nblk, check, gamma, out6);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// accelerated ascent step (one workgroup): scalars, step size, stop test,
+// gamma stage, projected step and momentum on lam'
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kScalarThreads) void agd_kernel(AgdArgs a)
+{
+    SolveState* st = a.st;
+    if (st->done) return;
+    __shared__ double red[9 * kSW];
+    __shared__ double v[9];
+    __shared__ double sc[4];   // eta, beta, advance, stop
+    reduce_scalars(a.obj_part, a.nchunks, a.blockpart, a.nblk, v, red);
+    const SolveParams& P = a.prm;
+    if (threadIdx.x == 0) {
+        const int64_t k = st->k;
+        const int64_t ks = st->ks;
+        const double gamma = st->gamma;
+        const double reg = 0.5 * gamma * v[1];
+        const double g = -v[0] + reg - v[3];
+        const double obj = v[2] + reg;
+        double eta = st->eta;
+        if (P.adaptive) {
+            if (ks > 0 && v[6] > 0.0) {
+                const double Lh = sqrt(v[5]) / sqrt(v[6]);
+                eta = (Lh > 0.0 && 1.0 / Lh < st->eta_cap) ? 1.0 / Lh : st->eta_cap;
+            }
+        } else {
+            eta = st->eta_cap;
+        }
+        double rel = NAN;
+        st->g = g;
+        st->obj = obj;
+        st->gamma_eval = gamma;
+        st->stage_eval = st->stage;
+        st->gnorm = sqrt(v[4]);
+        if (a.check) {
+            const double Pv = obj + v[7];
+            rel = (Pv - g) / fmax(1.0, fabs(g));
+            st->P = Pv;
+            st->rel_gap = rel;
+            st->max_infeas = v[8];
+        }
+        if (a.trace) {
+            double* row = a.trace + k * 6;
+            row[0] = g;
+            row[1] = rel;
+            row[2] = eta;
+            row[3] = gamma;
+            row[4] = (double)st->stage;
+            row[5] = sqrt(v[4]);
+        }
+        double stop = 0.0, advance = 0.0, beta = 0.0;
+        if (!isfinite(g)) {
+            st->status = 5;
+            st->done = 1;
+            stop = 1.0;
+        } else {
+            const int last = st->stage == P.n_stages - 1;
+            if (a.check && last && rel <= P.tol) {
+                st->converged = 1;
+                st->done = 1;
+                st->k = k + 1;
+                stop = 1.0;
+            } else {
+                const double tm = st->tm;
+                const double tn = P.momentum ? 0.5 * (1.0 + sqrt(1.0 + 4.0 * tm * tm)) : 1.0;
+                beta = P.momentum ? (tm - 1.0) / tn : 0.0;
+                if (!last) {
+                    if (P.stage_iters > 0 && ks + 1 >= P.stage_iters) advance = 1.0;
+                    if (a.check && P.stage_tol > 0.0 && rel <= P.stage_tol) advance = 1.0;
+                }
+                st->eta = eta;
+                if (advance != 0.0) {
+                    const double gnew = P.gamma0 * pow(P.gamma_final / P.gamma0,
+                                                       (double)(st->stage + 1) / (double)(P.n_stages - 1));
+                    st->eta = eta * gnew / gamma;
+                    st->eta_cap = P.max_step * gnew / P.gamma0;
+                    st->gamma = gnew;
+                    st->stage += 1;
+                    st->tm = 1.0;
+                    st->ks = 0;
+                } else {
+                    st->tm = tn;
+                    st->ks = ks + 1;
+                }
+                st->k = k + 1;
+                if (k + 1 >= P.max_iters) st->done = 1;
+            }
+        }
+        sc[0] = eta;
+        sc[1] = beta;
+        sc[2] = advance;
+        sc[3] = stop;
+    }
+    __syncthreads();
+    if (sc[3] != 0.0) return;
+    const double eta = sc[0], beta = sc[1];
+    const bool adv = sc[2] != 0.0;
+    for (int j = threadIdx.x; j < a.J; j += blockDim.x) {
+        const double yj = a.y[j], Gj = a.G[j];
+        double ln = yj + eta * Gj;
+        ln = ln > 0.0 ? ln : 0.0;
+        a.yp[j] = yj;
+        a.Gp[j] = Gj;
+        double yn;
+        if (adv) {
+            yn = ln;
+        } else {
+            const double z = ln + beta * (ln - a.lam[j]);
+            yn = z > 0.0 ? z : 0.0;
+        }
+        a.lam[j] = ln;
+        a.y[j] = yn;
+        a.lam_eval[j] = a.D[j] * yn;
+    }
+}
+
+hipError_t launch_agd(const AgdArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(agd_kernel, dim3(1), dim3(kScalarThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ void permute_in_kernel(const double* src, const int32_t* orig, int J, double* dst)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < J) dst[j] = src[orig[j]];
+}
+
+hipError_t launch_permute_in(const double* src, const int32_t* orig, int J, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(permute_in_kernel, dim3((J + 255) / 256), dim3(256), 0, s, src, orig, J, dst);
+    return hipGetLastError();
+}
+
+__global__ void solve_init_kernel(SolveState* st, SolveParams prm, const double* lam_in,
+                                  const int32_t* orig, const double* D, int J, double* lam, double* y,
+                                  double* yp, double* G, double* Gp, double* lam_eval)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < J) {
+        double v = 0.0;
+        if (lam_in) {
+            v = lam_in[orig[j]] / D[j];
+            v = v > 0.0 ? v : 0.0;
+        }
+        lam[j] = v;
+        y[j] = v;
+        yp[j] = v;
+        G[j] = 0.0;
+        Gp[j] = 0.0;
+        lam_eval[j] = D[j] * v;
+    }
+    if (j == 0) {
+        st->gamma = prm.gamma0;
+        st->eta = prm.init_step;
+        st->eta_cap = prm.max_step;
+        st->tm = 1.0;
+        st->g = NAN;
+        st->P = NAN;
+        st->rel_gap = NAN;
+        st->max_infeas = NAN;
+        st->gnorm = NAN;
+        st->obj = NAN;
+        st->gamma_eval = prm.gamma0;
+        st->stage_eval = 0;
+        st->k = 0;
+        st->ks = 0;
+        st->stage = 0;
+        st->done = prm.max_iters <= 0 ? 1 : 0;
+        st->converged = 0;
+        st->status = 0;
+    }
+}
+
+hipError_t launch_solve_init(SolveState* st, SolveParams prm, const double* lam_in, const int32_t* orig,
+                             const double* D, int J, double* lam, double* y, double* yp, double* G,
+                             double* Gp, double* lam_eval, hipStream_t s)
+{
+    hipLaunchKernelGGL(solve_init_kernel, dim3((J + 255) / 256), dim3(256), 0, s, st, prm, lam_in, orig,
+                       D, J, lam, y, yp, G, Gp, lam_eval);
+    return hipGetLastError();
+}
+
+// lam_out (original rows, caller units) = D * (y if converged or no step was
+// taken, else y_prev): the last point whose g and gap were evaluated
+__global__ void solve_final_kernel(const SolveState* st, const double* y, const double* yp,
+                                   const int32_t* orig, const double* D, int J, double* lam_out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < J) {
+        const bool use_y = st->converged || st->k == 0;
+        lam_out[orig[j]] = D[j] * (use_y ? y[j] : yp[j]);
+    }
+}
+
+hipError_t launch_solve_final(const SolveState* st, const double* y, const double* yp,
+                              const int32_t* orig, const double* D, int J, double* lam_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(solve_final_kernel, dim3((J + 255) / 256), dim3(256), 0, s, st, y, yp, orig, D, J,
+                       lam_out);
+    return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,89 @@
+// Kernel arguments and launchers of libdualip (host and device see these).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace dl {
+
+// Fused dual-gradient pass: t = -(c + a lam_dst), blockwise projection,
+// per-destination sums of a x (and c x, v^2 x^2 on check passes), and the
+// per-edge part of the dual objective, sum_e c x + gamma/2 v^2 x^2.
+struct GradArgs {
+    const void* A;           // [n] storage type
+    const void* C;           // [n] storage type
+    const int32_t* dst;      // [n] relabelled destination
+    const float* U;          // [n] box bounds or null (no box block)
+    const float* IV;         // [n] 1/v^2 or null (v = 1)
+    const int64_t* perm;     // [n] original column of each stream position
+    double* X;               // [n] x output (original column order) or null
+    const Item* items;
+    const Chunk* chunks;
+    const double* lam;       // [J] lam in caller units, internal row order
+    const double* gamma_ptr; // device scalar, or null to use gamma_val
+    double gamma_val;
+    const int32_t* done;     // early-exit flag or null
+    int32_t J, K;            // rows; rows kept in LDS
+    int32_t nchunks, pad;
+    float* part;             // [planes][nchunks][K]
+    double* tail;            // [3][J] FP64 accumulators of rows >= K
+    double* obj_part;        // [nchunks][3]: sum t x, sum v^2 x^2, sum c x (check)
+};
+
+// Per-destination combination of the chunk partial sums.
+struct ReduceArgs {
+    const float* part;
+    int32_t nchunks, K, J, check, mode;   // mode 0: solve (lam' space), 1: evaluation
+    int32_t pad;
+    double* tail;
+    const double* b;         // [J] internal order
+    const double* D;         // [J] row scale
+    const double* lam;       // [J] the point evaluated, caller units
+    const double* y;         // solve: y', y'_prev, G'_prev
+    const double* yp;
+    const double* Gp;
+    double* G;               // solve: out G' = D (A x - b)
+    const int32_t* orig;     // evaluation: original row of internal row j
+    double* grad_out;        // evaluation: out (A x - b) in original row order
+    const double* gamma_ptr;
+    double gamma_val;
+    const int32_t* done;
+    double* blockpart;       // [gridDim.x][kRedStride]
+};
+
+struct AgdArgs {
+    SolveState* st;
+    SolveParams prm;
+    int32_t check, nchunks, nblk, J;
+    const double* obj_part;
+    const double* blockpart;
+    double* lam;
+    double* y;
+    double* yp;
+    double* G;
+    double* Gp;
+    double* lam_eval;
+    const double* D;
+    double* trace;           // [max_iters][6] or null
+};
+
+size_t grad_lds_bytes(int K, bool check);
+
+// storage: 0 f64, 1 f32, 2 bf16 (a, c)
+hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s);
+hipError_t launch_agd(const AgdArgs& a, hipStream_t s);
+hipError_t launch_permute_in(const double* src, const int32_t* orig, int J, double* dst,
+                             hipStream_t s);
+hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double* blockpart,
+                              int nblk, int check, double gamma, double* out6, hipStream_t s);
+hipError_t launch_solve_init(SolveState* st, SolveParams prm, const double* lam_in,
+                             const int32_t* orig, const double* D, int J, double* lam, double* y,
+                             double* yp, double* G, double* Gp, double* lam_eval, hipStream_t s);
+hipError_t launch_solve_final(const SolveState* st, const double* y, const double* yp,
+                              const int32_t* orig, const double* D, int J, double* lam_out,
+                              hipStream_t s);
+hipError_t set_grad_attributes(size_t max_lds);
+
+}  // namespace dl

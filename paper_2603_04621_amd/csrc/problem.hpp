@@ -1,0 +1,71 @@
+// Host-side state of a created problem and helpers shared by the ABI files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dualip.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+struct dl_problem {
+    int device = 0;
+    int64_t m = 0, n = 0, nblocks = 0;
+    int storage = 1;
+    int has_box = 0, has_w = 0, solve_ok = 1;
+    int J = 0, K = 0;                  // rows; rows resident in LDS
+    int nchunks = 0, nitems = 0, nblk2 = 0;
+    int64_t n_lane = 0, n_wave = 0, n_wg = 0;
+    int64_t stream_bytes = 0;
+    size_t device_bytes = 0;
+    // edge stream
+    void* A = nullptr;
+    void* C = nullptr;
+    int32_t* dst = nullptr;
+    float* U = nullptr;
+    float* IV = nullptr;
+    int64_t* perm = nullptr;
+    dl::Item* items = nullptr;
+    dl::Chunk* chunks = nullptr;
+    // rows (internal order)
+    double* b = nullptr;
+    double* D = nullptr;
+    int32_t* orig = nullptr;
+    // scratch of one evaluation
+    float* part = nullptr;
+    double* tail = nullptr;
+    double* obj_part = nullptr;
+    double* blockpart = nullptr;
+    double* lam_int = nullptr;
+    double* eval6 = nullptr;
+    // solve state
+    double *lam = nullptr, *y = nullptr, *yp = nullptr, *G = nullptr, *Gp = nullptr,
+           *lam_eval = nullptr;
+    dl::SolveState* st = nullptr;
+    dl::SolveState* st_host = nullptr;   // pinned mirror (2 slots)
+    std::vector<void*> allocs;
+};
+
+namespace dlh {
+
+void set_error(const char* fmt, ...);
+dl_status hip_fail(hipError_t e, const char* what);
+
+// gradient + reduction of one pass (mode 0: solve, 1: evaluation)
+dl::GradArgs grad_args(const dl_problem* p, const double* lam, const double* gamma_ptr,
+                       double gamma_val, const int32_t* done, double* X);
+dl::ReduceArgs reduce_args(const dl_problem* p, int check, int mode, const double* lam,
+                           const double* gamma_ptr, double gamma_val, const int32_t* done,
+                           double* grad_out);
+dl::AgdArgs agd_args(const dl_problem* p, const dl::SolveParams& prm, int check, double* trace);
+
+// enqueues one full iteration (gradient, reduction, ascent step)
+hipError_t enqueue_iteration(dl_problem* p, const dl::SolveParams& prm, int check, double* trace,
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
+dl_status check_solve_opts(const dl_solve_opts* o);
+dl::SolveParams make_params(const dl_solve_opts* o);
+bool is_check_iter(const dl_solve_opts* o, int64_t k);
+
+}  // namespace dlh

@@ -102,22 +102,22 @@ class Instance:
         A[self.dst, np.arange(self.n)] = self.a
         return A
 
-    def rounded(self, dtype) -> "Instance":
-        """Same instance with a, c (and u) rounded to ``dtype`` and widened back.
-
-        Used so a CPU check at float64 sees exactly the values a reduced-precision
-        store holds.
+    def rounded(self, storage: str) -> "Instance":
+        """Same instance with the values a device store of type ``storage``
+        ("f64", "f32", "bf16") holds: a and c rounded to that type, box bounds
+        to float32 (they are always stored as float32), widened back to float64.
+        Used so a CPU check at float64 sees exactly the stored values.
         """
         def rnd(v):
-            if v is None:
-                return None
-            if dtype == "bf16":
+            if storage == "bf16":
                 return _round_bf16(v)
-            return v.astype(dtype).astype(np.float64)
+            if storage == "f32":
+                return v.astype(np.float32).astype(np.float64)
+            return v.copy()
+        up = None if self.upper is None else self.upper.astype(np.float32).astype(np.float64)
         return Instance(self.m, self.n, self.dst, rnd(self.a), rnd(self.c), self.b,
-                        self.block_off, self.block_proj,
-                        None if self.upper is None else rnd(self.upper),
-                        self.name + f"[{dtype}]", self.seed, dict(self.meta))
+                        self.block_off, self.block_proj, up,
+                        self.name + f"[{storage}]", self.seed, dict(self.meta))
 
 
 def _round_bf16(v: np.ndarray) -> np.ndarray:

@@ -1,0 +1,135 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects malformed problems before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2603_04621_amd import _lib as L
+from paper_2603_04621_amd import api
+from paper_2603_04621_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "dualip.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(dl_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(n for n in names if not n.endswith("_t")))
+
+
+def test_header_symbols_are_exported():
+    names = header_functions()
+    assert len(names) >= 15
+    assert sorted(L.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_status_strings():
+    assert L.status_str(L.DL_OK) == "ok"
+    assert L.status_str(L.DL_ERR_UNSUPPORTED) == "unsupported"
+    assert L.status_str(99) == "unknown status"
+
+
+def small():
+    return I.random_small(5, I=30, J=6, dmax=5, box_frac=0.3)
+
+
+def test_validate_accepts_good_problem_both_layouts():
+    inst = small()
+    assert api.validate(inst, "csc") == L.DL_OK
+    assert api.validate(inst, "csr") == L.DL_OK
+    assert api.validate(inst, "csc", storage="bf16", primal_scale=1) == L.DL_OK
+
+
+def run_desc(mutate, opts_kw=None):
+    inst = small()
+    hd = api._HostDesc(inst, "csc")
+    mutate(hd, inst)
+    o, keep = api.make_opts(**(opts_kw or {}))
+    st = L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o))
+    return st, L.last_error()
+
+
+def test_validate_rejects_malformed_input():
+    def bad_row(hd, inst):
+        hd.idx[3] = inst.m
+    assert run_desc(bad_row)[0] == L.DL_ERR_INVALID_ARG
+
+    def nan_c(hd, inst):
+        hd.c[0] = np.nan
+    st, msg = run_desc(nan_c)
+    assert st == L.DL_ERR_INVALID_ARG and "c" in msg
+
+    def bad_blocks(hd, inst):
+        hd.block_off[2] = hd.block_off[1] - 1
+    assert run_desc(bad_blocks)[0] == L.DL_ERR_INVALID_ARG
+
+    def bad_end(hd, inst):
+        hd.block_off[-1] = inst.n - 1
+    assert run_desc(bad_end)[0] == L.DL_ERR_INVALID_ARG
+
+    def bad_proj(hd, inst):
+        hd.block_proj[0] = 7
+    assert run_desc(bad_proj)[0] == L.DL_ERR_INVALID_ARG
+
+    def neg_upper(hd, inst):
+        hd.upper = np.ones(inst.n)
+        hd.upper[1] = -1.0
+        hd.desc.upper = hd.upper.ctypes.data
+    assert run_desc(neg_upper)[0] == L.DL_ERR_INVALID_ARG
+
+    def m_zero(hd, inst):
+        hd.desc.m = 0
+    assert run_desc(m_zero)[0] == L.DL_ERR_INVALID_ARG
+
+    assert run_desc(lambda hd, inst: None, {"storage": "f32", "primal_scale": 2})[0] == \
+        L.DL_ERR_INVALID_ARG
+    st = L.lib().dl_problem_validate(None, None)
+    assert st == L.DL_ERR_INVALID_ARG
+
+
+def test_two_families_are_unsupported():
+    inst = small()
+    hd = api._HostDesc(inst, "csc")
+    # column 0 gets a second entry (a second matching family)
+    ptr = np.arange(inst.n + 1, dtype=np.int64)
+    ptr[1:] += 1
+    idx = np.concatenate([[0], hd.idx]).astype(np.int32)
+    val = np.concatenate([[1.0], hd.val])
+    hd.desc.ptr = ptr.ctypes.data
+    hd.desc.idx = idx.ctypes.data
+    hd.desc.val = val.ctypes.data
+    hd.desc.nnz = inst.n + 1
+    o, _ = api.make_opts()
+    st = L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o))
+    assert st == L.DL_ERR_UNSUPPORTED
+    assert "family" in L.last_error()
+
+
+def test_csr_duplicate_column_is_unsupported():
+    inst = small()
+    hd = api._HostDesc(inst, "csr")
+    hd.idx[1] = hd.idx[0]
+    o, _ = api.make_opts()
+    st = L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o))
+    assert st in (L.DL_ERR_UNSUPPORTED, L.DL_ERR_INVALID_ARG)
+
+
+def test_solve_opts_defaults():
+    o = L.SolveOpts()
+    L.lib().dl_solve_opts_init(ctypes.byref(o))
+    assert o.gamma0 == 0.01 and o.max_step == o.gamma0
+    assert o.init_step == pytest.approx(1e-2 * o.gamma0)
+    assert o.check_every == 10 and o.momentum == 1 and o.adaptive == 1
