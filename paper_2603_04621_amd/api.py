@@ -210,3 +210,78 @@ class Problem:
 
     def __exit__(self, *a):
         self.close()
+
+
+def batch_solve(problems, settings: SolveSettings, lam0s=None, stream=None):
+    """dl_batch_solve over several Problems: (list of lam tensors, list of SolveOutcome)."""
+    import torch
+    n = len(problems)
+    lams = []
+    st = SolveSettings(**{**settings.__dict__})
+    st.trace = False
+    for k, p in enumerate(problems):
+        lam = torch.zeros(p.m, dtype=torch.float64, device=p.device)
+        if lam0s is not None and lam0s[k] is not None:
+            lam.copy_(lam0s[k].to(device=p.device, dtype=torch.float64))
+            st.warm_start = 1
+        lams.append(lam)
+    hs = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    ls = (ctypes.c_void_p * n)(*[l.data_ptr() for l in lams])
+    res = (L.SolveResult * n)()
+    o = st.to_c(None)
+    L.check(L.lib().dl_batch_solve(hs, n, ctypes.byref(o), ls, res, _stream(stream)),
+            "dl_batch_solve", ok=(L.DL_OK, L.DL_ERR_NOT_CONVERGED))
+    return lams, [outcome(r) for r in res]
+
+
+class Server:
+    """dl_server: continuous batching of solve requests on the current device."""
+
+    def __init__(self, hbm_budget_bytes: float = 200e9, max_slots: int = 64):
+        h = ctypes.c_void_p()
+        L.check(L.lib().dl_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)),
+                "dl_server_create")
+        self._h = h
+        self._m = {}
+
+    def submit(self, inst, settings: SolveSettings, storage: str = "f32", **popts) -> int:
+        hd = _HostDesc(inst)
+        o, _keep = make_opts(storage, **popts)
+        t = ctypes.c_uint64()
+        L.check(L.lib().dl_server_submit(self._h, ctypes.byref(hd.desc), ctypes.byref(o),
+                                         ctypes.byref(settings.to_c(None)), ctypes.byref(t)),
+                "dl_server_submit")
+        self._m[t.value] = inst.m
+        return t.value
+
+    def times(self, ticket: int):
+        ts, tb, td = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        L.check(L.lib().dl_server_times(self._h, ticket, ctypes.byref(ts), ctypes.byref(tb),
+                                        ctypes.byref(td)), "dl_server_times")
+        return ts.value, tb.value, td.value
+
+    def poll(self, ticket: int):
+        """None while running; else (SolveOutcome, lam ndarray, (t_submit, t_start, t_done))."""
+        ts, tb, td = self.times(ticket)
+        if td <= 0.0:
+            return None
+        done = ctypes.c_int32()
+        r = L.SolveResult()
+        lam = np.empty(self._m[ticket])
+        L.check(L.lib().dl_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(r),
+                                       lam.ctypes.data), "dl_server_poll")
+        if not done.value:
+            return None
+        del self._m[ticket]
+        return outcome(r), lam, (ts, tb, td)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().dl_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

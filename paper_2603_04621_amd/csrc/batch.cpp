@@ -1,0 +1,250 @@
+// dl_batch_solve and the batched iteration driver (see batch.hpp).
+#include "batch.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+using namespace dl;
+using dlh::hip_fail;
+using dlh::set_error;
+
+namespace dlh {
+
+void BatchRunner::release()
+{
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(gtab_);
+    f(rtab_[0]);
+    f(rtab_[1]);
+    f(atab_[0]);
+    f(atab_[1]);
+    f(ctab_);
+    f(rbt_);
+    f(ndone_dev_);
+    f(st_dev_);
+    if (ndone_host_) (void)hipHostFree(ndone_host_);
+    gtab_ = nullptr;
+    rtab_[0] = rtab_[1] = nullptr;
+    atab_[0] = atab_[1] = nullptr;
+    ctab_ = rbt_ = nullptr;
+    ndone_dev_ = ndone_host_ = nullptr;
+    st_dev_ = nullptr;
+    st_cap_ = 0;
+    probs_.clear();
+    groups_.clear();
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
+{
+    hipError_t e = hipMalloc((void**)dst, std::max<size_t>(1, v.size()) * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return e;
+}
+
+dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::vector<SolveParams>& prm,
+                             hipStream_t s)
+{
+    release();
+    probs_ = probs;
+    const int n = (int)probs.size();
+    std::vector<GradArgs> g(n);
+    std::vector<ReduceArgs> r0(n), r1(n);
+    std::vector<AgdArgs> a0(n), a1(n);
+    for (int k = 0; k < n; ++k) {
+        dl_problem* p = probs[k];
+        g[k] = grad_args(p, p->lam_eval, &p->st->gamma, 0.0, &p->st->done, nullptr);
+        r0[k] = reduce_args(p, 0, 0, p->lam_eval, &p->st->gamma, 0.0, &p->st->done, nullptr);
+        r1[k] = reduce_args(p, 1, 0, p->lam_eval, &p->st->gamma, 0.0, &p->st->done, nullptr);
+        a0[k] = agd_args(p, prm[k], 0, nullptr);
+        a1[k] = agd_args(p, prm[k], 1, nullptr);
+    }
+    // groups by kernel variant; within a group the largest problems go first
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (int k = 0; k < n; ++k) by[{probs[k]->storage, probs[k]->has_w}].push_back(k);
+    std::vector<int2> ct, rb;
+    for (auto& kv : by) {
+        auto idx = kv.second;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return probs[a]->n > probs[b]->n; });
+        Group G;
+        G.storage = kv.first.first;
+        G.has_w = kv.first.second;
+        G.tail = 0;
+        G.lds = 0;
+        G.c0 = (int)ct.size();
+        // round-robin over problems so long chunks of big problems start early
+        int maxc = 0;
+        for (int k : idx) {
+            maxc = std::max(maxc, probs[k]->nchunks);
+            G.tail |= probs[k]->K < probs[k]->J;
+            G.lds = std::max({G.lds, grad_lds_bytes(probs[k]->K, false), grad_lds_bytes(probs[k]->K, true)});
+        }
+        for (int c = 0; c < maxc; ++c)
+            for (int k : idx)
+                if (c < probs[k]->nchunks) ct.push_back(make_int2(k, c));
+        G.nblocks = (int)ct.size() - G.c0;
+        groups_.push_back(G);
+    }
+    for (int k = 0; k < n; ++k)
+        for (int b = 0; b < probs[k]->nblk2; ++b) rb.push_back(make_int2(k, b));
+    nrb_ = (int)rb.size();
+    hipError_t e;
+    if ((e = upload(&gtab_, g, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&rtab_[0], r0, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&rtab_[1], r1, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&atab_[0], a0, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&atab_[1], a1, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&ctab_, ct, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&rbt_, rb, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = hipMalloc((void**)&ndone_dev_, sizeof(int))) != hipSuccess) return hip_fail(e, "batch flag");
+    if ((e = hipHostMalloc((void**)&ndone_host_, sizeof(int), hipHostMallocDefault)) != hipSuccess) {
+        ndone_host_ = nullptr;
+        return hip_fail(e, "batch flag");
+    }
+    if ((e = hipMalloc((void**)&st_dev_, std::max(1, n) * sizeof(SolveState))) != hipSuccess)
+        return hip_fail(e, "batch states");
+    st_cap_ = (size_t)n;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "batch tables");
+    return DL_OK;
+}
+
+hipError_t BatchRunner::enqueue_iteration(int check, hipStream_t s) const
+{
+    hipError_t e;
+    for (const Group& G : groups_)
+        if ((e = launch_grad_batch(gtab_, ctab_ + G.c0, G.nblocks, G.lds, G.storage, check != 0, G.has_w != 0,
+                                   G.tail != 0, s)) != hipSuccess)
+            return e;
+    if ((e = launch_reduce_batch(rtab_[check ? 1 : 0], rbt_, nrb_, s)) != hipSuccess) return e;
+    return launch_agd_batch(atab_[check ? 1 : 0], (int)probs_.size(), s);
+}
+
+hipError_t BatchRunner::count_done(hipStream_t s, int* ndone)
+{
+    hipError_t e = launch_count_done(atab_[0], (int)probs_.size(), ndone_dev_, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ndone_host_, ndone_dev_, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) *ndone = *ndone_host_;
+    return e;
+}
+
+hipError_t BatchRunner::states(hipStream_t s, std::vector<SolveState>& out)
+{
+    out.resize(probs_.size());
+    hipError_t e = launch_gather_states(atab_[0], (int)probs_.size(), st_dev_, s);
+    if (e == hipSuccess && !out.empty())
+        e = hipMemcpyAsync(out.data(), st_dev_, out.size() * sizeof(SolveState), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+}  // namespace dlh
+
+namespace {
+struct GraphHolder {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    ~GraphHolder()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+}  // namespace
+
+#define TRY(call, what)                                  \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, const dl_solve_opts* o,
+                                    double* const* lambdas, dl_solve_result* out, void* hip_stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!probs || count < 1 || !lambdas || !out) { set_error("invalid batch arguments"); return DL_ERR_INVALID_ARG; }
+    dl_status st = dlh::check_solve_opts(o);
+    if (st != DL_OK) return st;
+    std::vector<dl_problem*> ps(probs, probs + count);
+    for (int k = 0; k < count; ++k) {
+        if (!ps[k] || !lambdas[k]) { set_error("NULL problem or lambda at %d", k); return DL_ERR_INVALID_ARG; }
+        if (!ps[k]->solve_ok) { set_error("problem %d has a < 0 or b < 0", k); return DL_ERR_UNSUPPORTED; }
+        for (int q = 0; q < k; ++q)
+            if (ps[q] == ps[k]) { set_error("problem %d appears twice in the batch", k); return DL_ERR_INVALID_ARG; }
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const SolveParams prm = dlh::make_params(o);
+    for (int k = 0; k < count; ++k) {
+        dl_problem* p = ps[k];
+        TRY(launch_solve_init(p->st, prm, o->warm_start ? lambdas[k] : nullptr, p->orig, p->D, p->J, p->lam, p->y,
+                              p->yp, p->G, p->Gp, p->lam_eval, s),
+            "init kernel");
+    }
+    dlh::BatchRunner br;
+    st = br.build(ps, std::vector<SolveParams>(count, prm), s);
+    if (st != DL_OK) return st;
+    const int64_t N = o->max_iters;
+    int64_t seg = o->graph_iters > 0 ? o->graph_iters : (o->check_every > 0 ? o->check_every : 16);
+    if (o->check_every > 0 && seg % o->check_every != 0) seg = o->check_every;
+    int64_t k = 0;
+    const int64_t nfull = N / seg;
+    if (nfull > 0) {
+        GraphHolder gh;
+        TRY(hipStreamCreateWithFlags(&gh.cap, hipStreamNonBlocking), "capture stream");
+        TRY(hipStreamBeginCapture(gh.cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        for (int64_t q = 0; q < seg; ++q) {
+            const int check = o->check_every > 0 && (q + 1) % o->check_every == 0;
+            hipError_t e = br.enqueue_iteration(check, gh.cap);
+            if (e != hipSuccess) {
+                hipGraph_t gtmp = nullptr;
+                (void)hipStreamEndCapture(gh.cap, &gtmp);
+                if (gtmp) (void)hipGraphDestroy(gtmp);
+                return hip_fail(e, "capture batch iteration");
+            }
+        }
+        TRY(hipStreamEndCapture(gh.cap, &gh.graph), "end capture");
+        TRY(hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0), "instantiate graph");
+        for (int64_t gi = 0; gi < nfull; ++gi) {
+            TRY(hipGraphLaunch(gh.exec, s), "graph launch");
+            k += seg;
+            // poll every few replays (the check itself waits for the stream)
+            if ((gi & 3) == 3 || gi == nfull - 1) {
+                int nd = 0;
+                TRY(br.count_done(s, &nd), "poll");
+                if (nd == count) break;
+            }
+        }
+    }
+    for (; k < N; ++k) TRY(br.enqueue_iteration(dlh::is_check_iter(o, k) ? 1 : 0, s), "batch iteration");
+    for (int q = 0; q < count; ++q) {
+        dl_problem* p = ps[q];
+        TRY(launch_solve_final(p->st, p->y, p->yp, p->orig, p->D, p->J, lambdas[q], s), "final kernel");
+    }
+    std::vector<SolveState> fs;
+    TRY(br.states(s, fs), "read states");
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    dl_status worst = DL_OK;
+    for (int q = 0; q < count; ++q) {
+        dl_solve_result& r = out[q];
+        std::memset(&r, 0, sizeof r);
+        r.converged = fs[q].converged;
+        r.stage = fs[q].stage_eval;
+        r.iters = fs[q].k;
+        r.gamma = fs[q].gamma_eval;
+        r.g = fs[q].g;
+        r.P = fs[q].P;
+        r.rel_gap = fs[q].rel_gap;
+        r.max_infeas = fs[q].max_infeas;
+        r.seconds = secs;
+        r.status = fs[q].status == 5 ? DL_ERR_NUMERIC : (fs[q].converged ? DL_OK : DL_ERR_NOT_CONVERGED);
+        if (r.status != DL_OK && worst == DL_OK) worst = r.status;
+    }
+    if (worst != DL_OK) set_error("some problems did not converge");
+    return worst;
+}

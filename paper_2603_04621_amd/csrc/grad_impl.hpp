@@ -275,11 +275,11 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
     // unconditional and the wave issues them back to back), t in FP64
     // (in tiles of 8 rows with a scheduling fence between them, which caps the
     // registers the compiler spends on loads in flight)
-    constexpr int T = P < 8 ? P : 8;
+    constexpr int T = P < 8 ? P : 8;   // the last tile may be partial (P = 12)
 #pragma unroll
     for (int k0 = 0; k0 < P; k0 += T) {
 #pragma unroll
-        for (int k = k0; k < k0 + T; ++k) {
+        for (int k = k0; k < k0 + T && k < P; ++k) {
             const int kk = k < d ? k : d - 1;
             const uint32_t off = (uint32_t)(lc + kk * nb);
             av[k] = Val<VT>::cvt(ldo(A, off));
@@ -631,7 +631,7 @@ __device__ __forceinline__ void wave_dispatch(const GradArgs& g, const Item& it,
 }
 
 template <typename VT, bool CHECK, bool HASW, bool TAIL>
-__global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
+__device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
 {
     if (g.done && *g.done) return;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
     }
     __syncthreads();
 
-    const Chunk ch = g.chunks[blockIdx.x];
+    const Chunk ch = g.chunks[chunk];
     Obj ob = {0.0, 0.0, 0.0};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int i = ch.a0 + wave; i < ch.a1; i += kWaves) {
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
 
     // flush: this chunk's row of partial sums, and its objective part
     const int64_t plane = (int64_t)g.nchunks * K;
-    float* row = g.part + (int64_t)blockIdx.x * K;
+    float* row = g.part + (int64_t)chunk * K;
     for (int j = threadIdx.x; j < K; j += kWG) {
         row[j] = s.hg[j];
         if (CHECK) {
@@ -710,10 +710,26 @@ __global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
             b += s.red[kWaves + i];
             c += s.red[2 * kWaves + i];
         }
-        g.obj_part[3 * blockIdx.x] = a;
-        g.obj_part[3 * blockIdx.x + 1] = b;
-        g.obj_part[3 * blockIdx.x + 2] = c;
+        g.obj_part[3 * chunk] = a;
+        g.obj_part[3 * chunk + 1] = b;
+        g.obj_part[3 * chunk + 2] = c;
     }
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+__global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
+{
+    grad_body<VT, CHECK, HASW, TAIL>(g, blockIdx.x);
+}
+
+// batched form: workgroup b runs chunk ct[b].y of problem ct[b].x
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+__global__ __launch_bounds__(kWG) void grad_kernel_batch(const GradArgs* __restrict__ tab,
+                                                          const int2* __restrict__ ct)
+{
+    const int2 e = ct[blockIdx.x];
+    const GradArgs g = tab[e.x];
+    grad_body<VT, CHECK, HASW, TAIL>(g, e.y);
 }
 
 template <typename VT, bool CHECK, bool HASW, bool TAIL>
@@ -735,12 +751,36 @@ hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t
     return hipErrorInvalidValue;
 }
 
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+static hipError_t launch_grad_batch_t(const GradArgs* tab, const int2* ct, int nblocks, size_t lds,
+                                      hipStream_t s)
+{
+    hipLaunchKernelGGL((grad_kernel_batch<VT, CHECK, HASW, TAIL>), dim3(nblocks), dim3(kWG), lds, s, tab,
+                       ct);
+    return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_grad_batch_vt(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
+                                bool has_w, bool tail, hipStream_t s)
+{
+#define DL_L(C, W, T) \
+    if (check == C && has_w == W && tail == T) return launch_grad_batch_t<VT, C, W, T>(tab, ct, nblocks, lds, s);
+    DL_L(false, false, false) DL_L(false, false, true) DL_L(false, true, false) DL_L(false, true, true)
+    DL_L(true, false, false) DL_L(true, false, true) DL_L(true, true, false) DL_L(true, true, true)
+#undef DL_L
+    return hipErrorInvalidValue;
+}
+
 template <typename VT>
 hipError_t set_grad_attributes_vt(size_t lds)
 {
     hipError_t e = hipSuccess, r;
 #define DL_A(C, W, T)                                                                        \
     r = hipFuncSetAttribute((const void*)grad_kernel<VT, C, W, T>,                          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+    if (r != hipSuccess) e = r;                                                              \
+    r = hipFuncSetAttribute((const void*)grad_kernel_batch<VT, C, W, T>,                    \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
     if (r != hipSuccess) e = r;
     DL_A(false, false, false) DL_A(false, false, true) DL_A(false, true, false) DL_A(false, true, true)
@@ -751,6 +791,8 @@ hipError_t set_grad_attributes_vt(size_t lds)
 
 #define DL_INSTANTIATE_GRAD(VT)                                                              \
     template hipError_t launch_grad_vt<VT>(const GradArgs&, bool, bool, hipStream_t);     \
+    template hipError_t launch_grad_batch_vt<VT>(const GradArgs*, const int2*, int, size_t, bool, \
+                                                 bool, bool, hipStream_t);                  \
     template hipError_t set_grad_attributes_vt<VT>(size_t);
 
 

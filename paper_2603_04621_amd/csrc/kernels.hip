@@ -49,6 +49,20 @@ template <typename VT>
 hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s);
 template <typename VT>
 hipError_t set_grad_attributes_vt(size_t lds);
+template <typename VT>
+hipError_t launch_grad_batch_vt(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
+                                bool has_w, bool tail, hipStream_t s);
+
+hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, int storage,
+                             bool check, bool has_w, bool tail, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    switch (storage) {
+    case 0: return launch_grad_batch_vt<double>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    case 1: return launch_grad_batch_vt<float>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    default: return launch_grad_batch_vt<uint16_t>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    }
+}
 
 size_t grad_lds_bytes(int K, bool check)
 {
@@ -78,12 +92,12 @@ hipError_t set_grad_attributes(size_t lds)
 // ---------------------------------------------------------------------------
 // per-destination combination of the chunk partials (fixed order)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r)
+__device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
 {
     if (r.done && *r.done) return;
     __shared__ double sh[3][4][64];
     const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int j = blockIdx.x * 64 + l;
+    const int j = blk * 64 + l;
     const int planes = r.check ? 3 : 1;
     const int64_t plane = (int64_t)r.nchunks * r.K;
     for (int p = 0; p < planes; ++p) {
@@ -148,15 +162,32 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r)
     for (int i = 0; i < 5; ++i) S[i] = wave_sum(S[i]);
     S[5] = wave_max(S[5]);
     if (l == 0) {
-        double* out = r.blockpart + (int64_t)blockIdx.x * kRedStride;
+        double* out = r.blockpart + (int64_t)blk * kRedStride;
 #pragma unroll
         for (int i = 0; i < 6; ++i) out[i] = S[i];
     }
 }
 
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) { reduce_body(r, blockIdx.x); }
+
+// batched form: block b reduces row block rt[b].y of problem rt[b].x
+__global__ __launch_bounds__(256) void reduce_kernel_batch(const ReduceArgs* __restrict__ tab,
+                                                           const int2* __restrict__ rt)
+{
+    const int2 e = rt[blockIdx.x];
+    const ReduceArgs r = tab[e.x];
+    reduce_body(r, e.y);
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_kernel, dim3(nblk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceArgs* tab, const int2* rt, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel_batch, dim3(nblocks), dim3(256), 0, s, tab, rt);
     return hipGetLastError();
 }
 
@@ -237,7 +268,7 @@ hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double*
 // accelerated ascent step (one workgroup): scalars, step size, stop test,
 // gamma stage, projected step and momentum on lam'
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kScalarThreads) void agd_kernel(AgdArgs a)
+__device__ __forceinline__ void agd_body(const AgdArgs& a)
 {
     SolveState* st = a.st;
     if (st->done) return;
@@ -350,9 +381,24 @@ __global__ __launch_bounds__(kScalarThreads) void agd_kernel(AgdArgs a)
     }
 }
 
+__global__ __launch_bounds__(kScalarThreads) void agd_kernel(AgdArgs a) { agd_body(a); }
+
+// batched form: workgroup b steps problem b
+__global__ __launch_bounds__(kScalarThreads) void agd_kernel_batch(const AgdArgs* __restrict__ tab)
+{
+    const AgdArgs a = tab[blockIdx.x];
+    agd_body(a);
+}
+
 hipError_t launch_agd(const AgdArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(agd_kernel, dim3(1), dim3(kScalarThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_agd_batch(const AgdArgs* tab, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(agd_kernel_batch, dim3(count), dim3(kScalarThreads), 0, s, tab);
     return hipGetLastError();
 }
 
@@ -437,6 +483,40 @@ hipError_t launch_solve_final(const SolveState* st, const double* y, const doubl
 {
     hipLaunchKernelGGL(solve_final_kernel, dim3((J + 255) / 256), dim3(256), 0, s, st, y, yp, orig, D, J,
                        lam_out);
+    return hipGetLastError();
+}
+
+// number of finished problems of a batch (one workgroup)
+__global__ __launch_bounds__(256) void count_done_kernel(const AgdArgs* __restrict__ tab, int count, int* out)
+{
+    __shared__ int part[256];
+    int n = 0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) n += tab[i].st->done ? 1 : 0;
+    part[threadIdx.x] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
+        *out = t;
+    }
+}
+
+hipError_t launch_count_done(const AgdArgs* tab, int count, int* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(count_done_kernel, dim3(1), dim3(256), 0, s, tab, count, out);
+    return hipGetLastError();
+}
+
+// copies every problem's state into one contiguous array
+__global__ void gather_states_kernel(const AgdArgs* __restrict__ tab, int count, SolveState* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = *tab[i].st;
+}
+
+hipError_t launch_gather_states(const AgdArgs* tab, int count, SolveState* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_states_kernel, dim3((count + 63) / 64), dim3(64), 0, s, tab, count, out);
     return hipGetLastError();
 }
 

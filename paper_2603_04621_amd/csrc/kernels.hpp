@@ -86,4 +86,12 @@ hipError_t launch_solve_final(const SolveState* st, const double* y, const doubl
                               hipStream_t s);
 hipError_t set_grad_attributes(size_t max_lds);
 
+// batched forms: tables of per-problem argument blocks in device memory
+hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, int storage,
+                             bool check, bool has_w, bool tail, hipStream_t s);
+hipError_t launch_reduce_batch(const ReduceArgs* tab, const int2* rt, int nblocks, hipStream_t s);
+hipError_t launch_agd_batch(const AgdArgs* tab, int count, hipStream_t s);
+hipError_t launch_count_done(const AgdArgs* tab, int count, int* out, hipStream_t s);
+hipError_t launch_gather_states(const AgdArgs* tab, int count, SolveState* out, hipStream_t s);
+
 }  // namespace dl

@@ -1,0 +1,79 @@
+"""Batched solves: every LP of a batch reproduces its solo dl_solve run.
+
+Each problem keeps its own chunking, reduction order and FP64 state inside the
+fused batched launches; the only difference between two runs is the order in
+which the waves of a workgroup add into the f32 LDS partial sums (atomics), so
+results agree to rounding, not bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2603_04621_amd import instances as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def same_solve(k, lam1, r1, lam2, r2, s):
+    """Two runs of one solve agree to rounding: the same stopping iteration
+    (or one check period apart when a gap test sits at the tolerance), the
+    same status, and g and lam equal to rounding."""
+    assert r2.converged == r1.converged, (k, r1, r2)
+    if r2.iters == r1.iters:
+        assert abs(r2.g - r1.g) <= 1e-9 * max(1.0, abs(r1.g)), (k, r1.g, r2.g)
+        assert np.max(np.abs(lam2 - lam1), initial=0.0) <= 1e-5 * max(1.0, np.abs(lam1).max(initial=0.0))
+    else:
+        assert abs(r2.iters - r1.iters) <= s.check_every, (k, r1.iters, r2.iters)
+        if r1.converged:
+            assert r1.rel_gap <= s.tol_rel_gap and r2.rel_gap <= s.tol_rel_gap
+
+
+def make_batch(count=10, seed=4621100):
+    sizes = I.batch_sizes(count, lo=1e3, hi=2e5, seed=seed)
+    insts = [I.batch_member(int(s), k, seed=seed, capacity="greedy") for k, s in enumerate(sizes)]
+    # one mixed-projection member with a heavier tail
+    insts.append(I.heavy(I=3000, J=400, dmax=700, capacity="greedy"))
+    return insts
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_equals_solo(dev, storage):
+    from paper_2603_04621_amd.api import Problem, SolveSettings, batch_solve
+    insts = make_batch()
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=3, stage_iters=400, stage_tol=1e-3,
+                      tol_rel_gap=1e-4, max_iters=1500, check_every=10, max_step=1e-1,
+                      init_step=1e-3)
+    probs = [Problem(x, storage=storage) for x in insts]
+    solo = [p.solve(s) for p in probs]
+    lams, outs = batch_solve(probs, s)
+    for k, ((l1, r1), l2, r2) in enumerate(zip(solo, lams, outs)):
+        same_solve(k, l1.cpu().numpy(), r1, l2.cpu().numpy(), r2, s)
+    assert sum(r.converged for r in outs) >= len(outs) - 1
+    for p in probs:
+        p.close()
+
+
+def test_batch_matches_oracle_member(dev):
+    """One batched member against the CPU oracle directly (FP64 storage)."""
+    from oracle import oracle as O
+    from paper_2603_04621_amd.api import Problem, SolveSettings, batch_solve
+    insts = make_batch(count=4, seed=4621200)
+    s = SolveSettings(gamma0=1e-2, gamma_final=1e-2, tol_rel_gap=0.0, max_iters=200,
+                      check_every=10, max_step=1e-2, init_step=1e-4)
+    probs = [Problem(x, storage="f64") for x in insts]
+    lams, outs = batch_solve(probs, s)
+    k = 2
+    r_or = O.solve(insts[k], O.SolveOpts(gamma0=1e-2, gamma_final=1e-2, tol_rel_gap=0.0,
+                                         max_iters=200, check_every=10, max_step=1e-2,
+                                         init_step=1e-4))
+    assert abs(outs[k].g - r_or.g) <= 1e-6 * max(1.0, abs(r_or.g))
+    la = lams[k].cpu().numpy()
+    assert np.max(np.abs(la - r_or.lam)) <= 1e-5 * max(1.0, np.max(np.abs(r_or.lam)))
+    for p in probs:
+        p.close()

@@ -1,0 +1,63 @@
+"""Serving: requests submitted while others run are admitted as slots free
+up, run in shared fused ticks, and each result equals the request's solo
+dl_solve result (to rounding: see test_gpu_batch)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2603_04621_amd import instances as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_solo():
+    from paper_2603_04621_amd.api import Problem, Server, SolveSettings
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(3)
+    sizes = np.rint(np.exp(rng.uniform(np.log(2e3), np.log(6e4), size=12))).astype(int)
+    insts = [I.serve_member(int(s), k, capacity="greedy") for k, s in enumerate(sizes)]
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=3, stage_iters=300, stage_tol=1e-3,
+                      tol_rel_gap=1e-4, max_iters=2000, check_every=10, max_step=1e-1,
+                      init_step=1e-3)
+    solo = []
+    for x in insts:
+        with Problem(x) as p:
+            lam, r = p.solve(s)
+            solo.append((lam.cpu().numpy(), r))
+    srv = Server(hbm_budget_bytes=8e9, max_slots=4)      # fewer slots than requests
+    tickets = []
+    for k, x in enumerate(insts):
+        tickets.append(srv.submit(x, s))
+        time.sleep(0.002 * (k % 3))                      # arrivals while others run
+    res = {}
+    t_end = time.time() + 120
+    while len(res) < len(tickets) and time.time() < t_end:
+        for t in tickets:
+            if t not in res:
+                out = srv.poll(t)
+                if out is not None:
+                    res[t] = out
+        time.sleep(0.001)
+    srv.close()
+    assert len(res) == len(tickets)
+    starts = sorted(v[2][1] for v in res.values())
+    dones = sorted(v[2][2] for v in res.values())
+    assert starts[-1] > dones[0], "later requests should be admitted after earlier ones finish"
+    from test_gpu_batch import same_solve
+    for k, t in enumerate(tickets):
+        r_srv, lam_srv, _ = res[t]
+        lam_solo, r_solo = solo[k]
+        same_solve(k, lam_solo, r_solo, lam_srv, r_srv, s)
+
+
+def test_server_rejects_oversized_request():
+    from paper_2603_04621_amd import _lib as L
+    from paper_2603_04621_amd.api import Server, SolveSettings
+    torch.cuda.set_device(0)
+    srv = Server(hbm_budget_bytes=1 << 20, max_slots=2)
+    with pytest.raises(L.DualipError) as e:
+        srv.submit(I.large(I=200_000, J=1000), SolveSettings())
+    assert e.value.status == L.DL_ERR_UNSUPPORTED
+    srv.close()
