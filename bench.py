@@ -73,6 +73,139 @@ def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0):
                       f"not included"}
 
 
+def load_or_generate(I, args):
+    fields = ("dst", "a", "c", "b", "block_off", "block_proj")
+    tag = f"large_{args.sources}_{args.dests}"
+    if args.cache:
+        d = os.path.join(args.cache, tag)
+        if all(os.path.exists(os.path.join(d, f + ".npy")) for f in fields):
+            arr = {f: np.load(os.path.join(d, f + ".npy")) for f in fields}
+            return I.Instance(args.dests, int(arr["dst"].shape[0]), arr["dst"], arr["a"], arr["c"],
+                              arr["b"], arr["block_off"], arr["block_proj"], None, "large",
+                              I.SEED_BASE + 2)
+    inst = I.large(I=args.sources, J=args.dests)
+    if args.cache:
+        d = os.path.join(args.cache, tag)
+        os.makedirs(d, exist_ok=True)
+        for f in fields:
+            np.save(os.path.join(d, f + ".npy"), getattr(inst, f))
+    return inst
+
+
+def systems(args, log):
+    """Batched and served solves against one-at-a-time plain solves, all to
+    rel_gap 1e-4 with the same gamma continuation (binding capacities)."""
+    import threading
+    import torch
+    from paper_2603_04621_amd import instances as I
+    from paper_2603_04621_amd.api import Problem, Server, SolveSettings, batch_solve
+
+    st = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=5, stage_iters=2000,
+                       stage_tol=1e-3, tol_rel_gap=1e-4, max_iters=20000, check_every=10,
+                       max_step=1e-1, init_step=1e-3)
+    out = {}
+    # ---- batched: the 256-LP workload (I log-uniform [1e3, hi])
+    sizes = I.batch_sizes(args.batch_count, 1e3, args.batch_hi)
+    t0 = time.perf_counter()
+    insts = [I.batch_member(int(n), k, capacity="greedy") for k, n in enumerate(sizes)]
+    log(f"batch: {len(insts)} LPs, {sum(x.n for x in insts)} nnz generated in "
+        f"{time.perf_counter() - t0:.1f}s")
+    probs = [Problem(x) for x in insts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [p.solve(st)[1] for p in probs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, bat = batch_solve(probs, st)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    for p in probs:
+        p.close()
+    out["batched"] = {
+        "workload": f"{len(insts)} matching LPs, I log-uniform [1e3, {args.batch_hi:.0e}], "
+                    f"J = I/200, degree 1+Poisson(9), Zipf(1.1), greedy-load capacities, "
+                    f"gamma 1e-1 -> 1e-3 in 5 stages, to rel_gap 1e-4",
+        "nnz_total": int(sum(x.n for x in insts)),
+        "solves_per_s": len(insts) / t_bat, "seconds": t_bat,
+        "sequential_solves_per_s": len(insts) / t_seq, "sequential_seconds": t_seq,
+        "speedup": t_seq / t_bat,
+        "converged": int(sum(r.converged for r in bat)),
+        "sequential_converged": int(sum(r.converged for r in seq)),
+        "max_rel_gap": float(max(r.rel_gap for r in bat)),
+        "iters_max": int(max(r.iters for r in bat)),
+    }
+    log(f"batched: {out['batched']}")
+    # ---- served: Poisson stream
+    arr = I.serve_stream(args.serve_count, rate=args.serve_rate, lo=1e4, hi=args.serve_hi)
+    t0 = time.perf_counter()
+    reqs = [I.serve_member(n, k, capacity="greedy") for k, (_, n) in enumerate(arr)]
+    log(f"serve: {len(reqs)} requests, {sum(x.n for x in reqs)} nnz generated in "
+        f"{time.perf_counter() - t0:.1f}s")
+    srv = Server(hbm_budget_bytes=200e9, max_slots=args.serve_slots)
+    tickets = [None] * len(reqs)
+    t_arr = [None] * len(reqs)
+    start = time.perf_counter()
+
+    def feeder():
+        for k, (ta, _) in enumerate(arr):
+            dt = start + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            t_arr[k] = time.perf_counter()
+            tickets[k] = srv.submit(reqs[k], st)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    lat, res = [None] * len(reqs), [None] * len(reqs)
+    left = set(range(len(reqs)))
+    while left:
+        for k in list(left):
+            if tickets[k] is None:
+                continue
+            o = srv.poll(tickets[k])
+            if o is not None:
+                res[k] = o
+                lat[k] = time.perf_counter() - t_arr[k]
+                left.discard(k)
+        time.sleep(0.0005)
+    th.join()
+    t_srv = time.perf_counter() - start
+    srv.close()
+    # one-at-a-time baseline: measured create + solve per request, first come
+    # first served on the same arrival times
+    svc = []
+    for x in reqs:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        with Problem(x) as p:
+            p.solve(st)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t1)
+    done_prev, seq_lat = 0.0, []
+    for (ta, _), sv in zip(arr, svc):
+        begin = max(ta, done_prev)
+        done_prev = begin + sv
+        seq_lat.append(done_prev - ta)
+    lat = np.array(lat)
+    seq_lat = np.array(seq_lat)
+    out["served"] = {
+        "workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate:g}/s, "
+                    f"I log-uniform [1e4, {args.serve_hi:.0e}], J = I/500, 70/30 simplex/box, "
+                    f"greedy-load capacities, to rel_gap 1e-4; {args.serve_slots} slots, "
+                    f"200 GB budget",
+        "solves_per_s": len(reqs) / t_srv,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "sequential_solves_per_s": len(reqs) / done_prev,
+        "sequential_p50_latency_s": float(np.percentile(seq_lat, 50)),
+        "sequential_p99_latency_s": float(np.percentile(seq_lat, 99)),
+        "converged": int(sum(r[0].converged for r in res)),
+    }
+    log(f"served: {out['served']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,9 +215,34 @@ def main():
     ap.add_argument("--dests", type=int, default=10_000)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-binding", action="store_true",
+                    help="skip the binding-capacity variant")
+    ap.add_argument("--systems", action="store_true",
+                    help="also measure batched and served solves")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-hi", type=float, default=1e6)
+    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-hi", type=float, default=5e5)
+    ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--cache", default=None,
+                    help="directory to save/load the generated instance (npy files)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        torch.cuda.set_device(0)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4,
+                          "launches": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
@@ -96,8 +254,8 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    inst = I.large(I=args.sources, J=args.dests)
-    log(f"generated {inst.n} nnz in {time.perf_counter() - t0:.1f}s")
+    inst = load_or_generate(I, args)
+    log(f"instance with {inst.n} nnz ready in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     prob = Problem(inst, storage=args.storage)
     info = prob.info()
@@ -105,20 +263,24 @@ def main():
 
     gamma = 1e-3
     # the solve the steps belong to: one gamma stage at the final gamma, the
-    # paper's step-size ratio, gap test every check_every iterations, no early
-    # stop (tol 0) so exactly `steps` iterations run
+    # paper's step-size ratio, gap test every check_every iterations; the gap
+    # never stops it (negative tolerance) so exactly `steps` iterations run
     def settings(iters):
         return SolveSettings(gamma0=gamma, gamma_final=gamma, max_iters=iters,
-                             check_every=args.check_every, tol_rel_gap=0.0, max_step=gamma,
+                             check_every=args.check_every, tol_rel_gap=-1.0, max_step=gamma,
                              init_step=1e-2 * gamma, time_kernels=1)
 
-    prob.solve(settings(args.warmup))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lam, r = prob.solve(settings(args.steps))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    assert r.iters == args.steps, r
+    def timed(p):
+        p.solve(settings(args.warmup))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, r = p.solve(settings(args.steps))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert r.iters == args.steps, r
+        return lam, r, el
+
+    lam, r, el = timed(prob)
     ms = el * 1e3 / args.steps
     ips = args.steps / el
     bytes_per = info["stream_bytes"]
@@ -153,10 +315,28 @@ def main():
         "final_g": r.g,
         "final_rel_gap": r.rel_gap,
     }
+    if not args.no_binding:
+        # same sparsity and values with the paper's greedy-load capacities
+        # (Appendix B), under which constraints bind and the prices move
+        lam_b = I.greedy_capacity(inst.dst, inst.a, inst.block_off, inst.m,
+                                  [inst.seed, 1, 2])
+        inst_b = I.Instance(inst.m, inst.n, inst.dst, inst.a, inst.c, lam_b, inst.block_off,
+                            inst.block_proj, None, "large-binding", inst.seed)
+        prob.close()
+        with Problem(inst_b, storage=args.storage) as pb:
+            _, rb, elb = timed(pb)
+        out["binding_variant"] = {
+            "capacity": "greedy load (Appendix B)", "iter_per_s": args.steps / elb,
+            "grad_kernel_ms": rb.grad_kernel_ms,
+            "achieved_gbs": bytes_per / (rb.grad_kernel_ms * 1e-3) / 1e9,
+            "final_rel_gap": rb.rel_gap}
+    lam_np = lam.cpu().numpy()
+    prob.close()
+    if args.systems:
+        out.update(systems(args, log))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(inst, lam.cpu().numpy(), gamma, args.cpu_budget)
-    prob.close()
+        out["cpu_baseline"] = cpu_baseline(inst, lam_np, gamma, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -157,7 +157,8 @@ dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, double gamma, do
  * stage change, which happens after stage_iters iterations (0 = never) or
  * when rel_gap <= stage_tol at a check (0 = never).  The gap is evaluated
  * every check_every iterations and at the last one (0 = never); the solve
- * stops in the last stage once rel_gap <= tol_rel_gap, or after max_iters.
+ * stops in the last stage once rel_gap <= tol_rel_gap (a negative tolerance
+ * never stops on the gap), or after max_iters.
  *   max_step, init_step  eta_max and the first step at gamma0, in lam' units
  *                        (after row normalization |A'|^2 = 1, so L = 1/gamma
  *                        and max_step = gamma0 is the classical 1/L).

@@ -309,9 +309,9 @@ static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, Hos
             }
         }
     });
-    // chunks: each kind list split by nonzeros
-    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0});
-    auto split = [&](int64_t first, int64_t count, bool a) {
+    // chunks: each kind's list split evenly by nonzeros
+    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0, 0, 0});
+    auto split = [&](int64_t first, int64_t count, int which) {
         std::vector<int64_t> pre((size_t)count + 1, 0);
         for (int64_t q = 0; q < count; ++q)
             pre[q + 1] = pre[q] + (int64_t)L.items[first + q].d * L.items[first + q].nb;
@@ -321,12 +321,14 @@ static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, Hos
             const int64_t target = (int64_t)((double)tot * (c + 1) / nchunks);
             const int64_t q0 = q;
             while (q < count && (c == nchunks - 1 || pre[q] + (pre[q + 1] - pre[q]) / 2 < target)) ++q;
-            if (a) { L.chunks[c].a0 = (int32_t)(first + q0); L.chunks[c].a1 = (int32_t)(first + q); }
-            else { L.chunks[c].b0 = (int32_t)(first + q0); L.chunks[c].b1 = (int32_t)(first + q); }
+            int32_t* r = which == 0 ? &L.chunks[c].a0 : (which == 1 ? &L.chunks[c].w0 : &L.chunks[c].b0);
+            r[0] = (int32_t)(first + q0);
+            r[1] = (int32_t)(first + q);
         }
     };
-    split(0, L.nA, true);
-    split(L.nA, L.nB, false);
+    split(0, L.n_lane, 0);
+    split(L.n_lane, L.n_wave, 1);
+    split(L.nA, L.nB, 2);
 }
 
 static int device_cus(int dev)
@@ -681,7 +683,7 @@ dl_status check_solve_opts(const dl_solve_opts* o)
     if (o->n_stages < 1) { set_error("n_stages must be >= 1"); return DL_ERR_INVALID_ARG; }
     if (o->max_iters < 0 || o->check_every < 0 || o->stage_iters < 0) { set_error("negative iteration count"); return DL_ERR_INVALID_ARG; }
     if (!(o->max_step > 0.0) || !(o->init_step > 0.0)) { set_error("steps must be positive"); return DL_ERR_INVALID_ARG; }
-    if (!(o->tol_rel_gap >= 0.0) || !(o->stage_tol >= 0.0)) { set_error("tolerances must be >= 0"); return DL_ERR_INVALID_ARG; }
+    if (std::isnan(o->tol_rel_gap) || !(o->stage_tol >= 0.0)) { set_error("invalid tolerance"); return DL_ERR_INVALID_ARG; }
     if (o->graph_iters < 0) { set_error("graph_iters must be >= 0"); return DL_ERR_INVALID_ARG; }
     return DL_OK;
 }

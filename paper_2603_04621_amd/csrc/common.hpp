@@ -9,7 +9,7 @@
 //   only read when x is requested).
 //
 //   Work items.  Blocks are grouped by projection type and degree d:
-//     LANE  d <= 16 (8 for FP64 storage): groups of up to 64 blocks of one
+//     LANE  d <= 32 (8 for FP64 storage): groups of up to 64 blocks of one
 //           exact degree; lane l of a
 //           wave owns block l of the group, whose k-th edge is stored at
 //           base + k*nb + l, so every load of the wave is one contiguous
@@ -19,8 +19,8 @@
 //     WG    d > 512: one workgroup per block, edge k at base + k.
 //
 //   Chunks.  The workgroups of the fused gradient kernel each take one
-//   chunk: a range of LANE/WAVE items (spread over the chunk's waves) and a
-//   range of WG items, balanced by nonzeros.  Each chunk owns one row of the
+//   chunk: an equal share (by nonzeros) of the LANE items, of the WAVE items
+//   (both spread over the chunk's waves) and of the WG items.  Each chunk owns one row of the
 //   per-destination partial-sum buffer, so results do not depend on timing.
 //
 //   Destinations.  Relabelled by descending degree; the first K (lds_rows)
@@ -33,7 +33,7 @@ namespace dl {
 
 constexpr int kWG = 512;                // threads of a gradient workgroup
 constexpr int kWaves = kWG / 64;
-constexpr int kLaneMaxDeg = 16;         // LANE items (registers: 16 edges per lane)
+constexpr int kLaneMaxDeg = 32;         // LANE items (registers: 32 edges per lane)
 constexpr int kLaneMaxDegF64 = 8;       // LANE items with FP64 storage
 constexpr int kWaveMaxDeg = 512;        // WAVE items (8 edges per lane)
 
@@ -48,8 +48,8 @@ struct Item {                // 16 bytes
 };
 static_assert(sizeof(Item) == 16, "Item layout");
 
-struct Chunk {               // wave items [a0, a1), workgroup items [b0, b1)
-    int32_t a0, a1, b0, b1;
+struct Chunk {               // lane groups [a0, a1), wave blocks [w0, w1), workgroup blocks [b0, b1)
+    int32_t a0, a1, w0, w1, b0, b1;
 };
 
 // Scalars of the iteration that live on the device (one per solve slot).

@@ -248,7 +248,7 @@ template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
 __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, const Lds& s,
                                            double gamma, Obj& ob)
 {
-    static_assert(P <= 16, "lane blocks hold at most 16 edges");
+    static_assert(P <= 32, "lane blocks hold at most 32 edges");
     using R = typename Val<VT>::reg;
     const int lane = threadIdx.x & 63;
     const int d = uni(it.d), nb = uni(it.nb);
@@ -273,9 +273,9 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
 
     // pass 1: loads (rows beyond d re-read row d-1, so every load is
     // unconditional and the wave issues them back to back), t in FP64
-    // (in tiles of 8 rows with a scheduling fence between them, which caps the
-    // registers the compiler spends on loads in flight)
-    constexpr int T = P < 8 ? P : 8;   // the last tile may be partial (P = 12)
+    // (in tiles of up to 16 rows with a scheduling fence between them: all
+    // loads of a tile are in flight together; P = 32 takes two round trips)
+    constexpr int T = P < 16 ? P : 16;
 #pragma unroll
     for (int k0 = 0; k0 < P; k0 += T) {
 #pragma unroll
@@ -297,12 +297,48 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
 
     // pass 2: simplex threshold in registers
     double tau = 0.0;
-    if (!BOX) {
+    if (!BOX && !HASW) {
+        // uniform weight w = 1/gamma: sum max(0, w t) > 1  <=>  sum max(0, t) > gamma,
+        // tau_0 = max(0, max t - gamma), tau <- (sum_S t - gamma) / |S|
+        double sp = 0.0, mt = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            sp += t[k] > 0.0 ? t[k] : 0.0;
+            mt = t[k] > mt ? t[k] : mt;
+        }
+        if (sp > gamma) {
+            tau = mt - gamma > 0.0 ? mt - gamma : 0.0;
+            double st = 0.0;
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const bool in = t[k] > tau;
+                st += in ? t[k] : 0.0;
+                n += in ? 1 : 0;
+            }
+#pragma unroll 1
+            for (int rep = 0; rep < 2 * P + 4; ++rep) {
+                const double tn = (st - gamma) / (double)n;
+                double st2 = 0.0;
+                int n2 = 0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const bool in = t[k] > tn;
+                    st2 += in ? t[k] : 0.0;
+                    n2 += in ? 1 : 0;
+                }
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                st = st2;
+                n = n2;
+            }
+        }
+    } else if (!BOX) {
         double s0 = 0.0, mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-            const double iw = HASW ? gamma / (double)iv[k] : gamma;
+            const double w = (double)iv[HASW ? k : 0] * inv_g;
+            const double iw = gamma / (double)iv[HASW ? k : 0];
             const double z = w * t[k];
             s0 += z > 0.0 ? z : 0.0;
             const double lo = t[k] - iw;
@@ -314,19 +350,20 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
             int n = 0;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                const double w = (double)iv[HASW ? k : 0] * inv_g;
                 const bool in = t[k] > tau;
                 sw += in ? w : 0.0;
                 swt += in ? w * t[k] : 0.0;
                 n += in ? 1 : 0;
             }
+#pragma unroll 1
             for (int rep = 0; rep < 2 * P + 4; ++rep) {
                 const double tn = (swt - 1.0) / sw;
                 double sw2 = 0.0, swt2 = 0.0;
                 int n2 = 0;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                    const double w = (double)iv[HASW ? k : 0] * inv_g;
                     const bool in = t[k] > tn;
                     sw2 += in ? w : 0.0;
                     swt2 += in ? w * t[k] : 0.0;
@@ -420,12 +457,52 @@ __device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, co
         if (CHECK) cv[k] = c;
     }
     double tau = 0.0;
-    if (!BOX) {
+    if (!BOX && !HASW) {
+        double sp = 0.0, mt = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < P2; ++k) {
+            sp += t[k] > 0.0 ? t[k] : 0.0;
+            mt = fmax(mt, t[k]);
+        }
+        sp = wave_sum(sp);
+        mt = wave_max(mt);
+        if (sp > gamma) {
+            tau = mt - gamma > 0.0 ? mt - gamma : 0.0;
+            double st = 0.0;
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < P2; ++k) {
+                const bool in = t[k] > tau;
+                st += in ? t[k] : 0.0;
+                n += in ? 1 : 0;
+            }
+            st = wave_sum(st);
+            n = wave_sum_i(n);
+#pragma unroll 1
+            for (int rep = 0; rep < 2 * 64 * P2 + 4; ++rep) {
+                const double tn = (st - gamma) / (double)n;
+                double st2 = 0.0;
+                int n2 = 0;
+#pragma unroll
+                for (int k = 0; k < P2; ++k) {
+                    const bool in = t[k] > tn;
+                    st2 += in ? t[k] : 0.0;
+                    n2 += in ? 1 : 0;
+                }
+                st2 = wave_sum(st2);
+                n2 = wave_sum_i(n2);
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                st = st2;
+                n = n2;
+            }
+        }
+    } else if (!BOX) {
         double s0 = 0.0, mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < P2; ++k) {
-            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-            const double iw = HASW ? gamma / (double)iv[k] : gamma;
+            const double w = (double)iv[HASW ? k : 0] * inv_g;
+            const double iw = gamma / (double)iv[HASW ? k : 0];
             const double z = w * t[k];
             s0 += z > 0.0 ? z : 0.0;
             mx = fmax(mx, t[k] - iw);
@@ -438,7 +515,7 @@ __device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, co
             int n = 0;
 #pragma unroll
             for (int k = 0; k < P2; ++k) {
-                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                const double w = (double)iv[HASW ? k : 0] * inv_g;
                 const bool in = t[k] > tau;
                 sw += in ? w : 0.0;
                 swt += in ? w * t[k] : 0.0;
@@ -447,13 +524,14 @@ __device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, co
             sw = wave_sum(sw);
             swt = wave_sum(swt);
             n = wave_sum_i(n);
+#pragma unroll 1
             for (int rep = 0; rep < 2 * 64 * P2 + 4; ++rep) {
                 const double tn = (swt - 1.0) / sw;
                 double sw2 = 0.0, swt2 = 0.0;
                 int n2 = 0;
 #pragma unroll
                 for (int k = 0; k < P2; ++k) {
-                    const double w = HASW ? (double)iv[k] * inv_g : inv_g;
+                    const double w = (double)iv[HASW ? k : 0] * inv_g;
                     const bool in = t[k] > tn;
                     sw2 += in ? w : 0.0;
                     swt2 += in ? w * t[k] : 0.0;
@@ -562,6 +640,7 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
                 }
             }
             wg_sum3(sw, swt, n, s.red);
+#pragma unroll 1
             for (int rep = 0; rep < 2 * d + 4; ++rep) {
                 const double tn = (swt - 1.0) / sw;
                 double sw2 = 0.0, swt2 = 0.0;
@@ -612,11 +691,15 @@ template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
 __device__ __forceinline__ void lane_dispatch(const GradArgs& g, const Item& it, const Lds& s,
                                               double gamma, Obj& ob)
 {
+    // FP64 storage keeps blocks of at most 8 edges in lanes (register budget)
+    constexpr bool W8 = sizeof(VT) == 8;
     const int d = it.d;
     if (d <= 4) lane_group<VT, CHECK, HASW, TAIL, BOX, 4>(g, it, s, gamma, ob);
-    else if (d <= 8 || sizeof(VT) == 8) lane_group<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
-    else if (d <= 12) lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 12>(g, it, s, gamma, ob);
-    else lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 16>(g, it, s, gamma, ob);
+    else if (d <= 8 || W8) lane_group<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
+    else if (d <= 12) lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, it, s, gamma, ob);
+    else if (d <= 16) lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, it, s, gamma, ob);
+    else if (d <= 24) lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 24>(g, it, s, gamma, ob);
+    else lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 32>(g, it, s, gamma, ob);
 }
 
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
@@ -667,14 +750,38 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     const Chunk ch = g.chunks[chunk];
     Obj ob = {0.0, 0.0, 0.0};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int i = ch.a0 + wave; i < ch.a1; i += kWaves) {
-        const Item it = g.items[i];
-        if (it.kind == ITEM_LANE) {
-            if (it.proj == 1) lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-            else lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
-        } else {
-            if (it.proj == 1) wave_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-            else wave_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+    // this chunk's share of the lane groups, then of the wave blocks (each
+    // kind is spread evenly over the chunks, so no chunk is left with a long
+    // run of the costlier wave blocks).  A wave takes items a0 + wave + r*kWaves;
+    // their descriptors arrive 64 at a time (lane r holds item r of the batch)
+    // and are broadcast with readlane, so a group waits on its data only.
+    for (int kind = 0; kind < 2; ++kind) {
+        const int i0 = kind == 0 ? ch.a0 : ch.w0;
+        const int i1 = kind == 0 ? ch.a1 : ch.w1;
+        const int nmine = i1 - i0 > wave ? (i1 - i0 - wave + kWaves - 1) / kWaves : 0;
+        for (int r0 = 0; r0 < nmine; r0 += 64) {
+            const int lane = threadIdx.x & 63;
+            const int my = i0 + wave + (r0 + lane) * kWaves;
+            Item mine = {0, 0, 0, 0, 0};
+            if (r0 + lane < nmine) mine = g.items[my];
+            const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
+            for (int r = 0; r < rn; ++r) {
+                Item it;
+                it.base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine.base >> 32), r) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)mine.base, r));
+                it.d = __builtin_amdgcn_readlane(mine.d, r);
+                const int nbk = __builtin_amdgcn_readlane((int)mine.nb | ((int)mine.kind << 16) | ((int)mine.proj << 24), r);
+                it.nb = (uint16_t)(nbk & 0xFFFF);
+                it.kind = (uint8_t)((nbk >> 16) & 0xFF);
+                it.proj = (uint8_t)((nbk >> 24) & 0xFF);
+                if (kind == 0) {
+                    if (it.proj == 1) lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
+                    else lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+                } else {
+                    if (it.proj == 1) wave_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
+                    else wave_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+                }
+            }
         }
     }
     for (int i = ch.b0; i < ch.b1; ++i) {

@@ -5,7 +5,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dualip.h"
+#include "dualip.h"
 #include "common.hpp"
 #include "kernels.hpp"
 
