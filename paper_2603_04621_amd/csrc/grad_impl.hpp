@@ -272,21 +272,29 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
     float iv[HASW ? P : 1];
 
     // pass 1: loads (rows beyond d re-read row d-1, so every load is
-    // unconditional and the wave issues them back to back), t in FP64
-    // (in tiles of up to 16 rows with a scheduling fence between them: all
-    // loads of a tile are in flight together; P = 32 takes two round trips)
+    // unconditional), then t in FP64.  The loads of a tile of up to 16 rows
+    // are all issued before the first use, behind a scheduling fence: left
+    // to itself the scheduler interleaves each row's loads with its use and
+    // the wave pays one memory round trip per row instead of one per tile.
     constexpr int T = P < 16 ? P : 16;
 #pragma unroll
     for (int k0 = 0; k0 < P; k0 += T) {
+        VT ar[T], cr[T];
 #pragma unroll
         for (int k = k0; k < k0 + T && k < P; ++k) {
             const int kk = k < d ? k : d - 1;
             const uint32_t off = (uint32_t)(lc + kk * nb);
-            av[k] = Val<VT>::cvt(ldo(A, off));
-            const R c = Val<VT>::cvt(ldo(C, off));
+            ar[k - k0] = ldo(A, off);
+            cr[k - k0] = ldo(C, off);
             jv[k] = ldo(Dst, off);
             if (BOX) uv[k] = ldo(U, off);
             if (HASW) iv[k] = ldo(IV, off);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = k0; k < k0 + T && k < P; ++k) {
+            av[k] = Val<VT>::cvt(ar[k - k0]);
+            const R c = Val<VT>::cvt(cr[k - k0]);
             const double lam = get_lam<CHECK, TAIL>(s, g, jv[k]);
             const double tk = -((double)c + (double)av[k] * lam);
             t[k] = (k < d && act) ? tk : -INFINITY;
@@ -442,15 +450,24 @@ __device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, co
     int jv[P2];
     float uv[BOX ? P2 : 1];
     float iv[HASW ? P2 : 1];
+    // all loads first, behind a scheduling fence (one round trip per block)
+    VT ar[P2], cr[P2];
 #pragma unroll
     for (int k = 0; k < P2; ++k) {
         const int e = lane + 64 * k;
         const uint32_t ee = (uint32_t)(e < d ? e : d - 1);
-        av[k] = Val<VT>::cvt(ldo(A, ee));
-        const R c = Val<VT>::cvt(ldo(C, ee));
+        ar[k] = ldo(A, ee);
+        cr[k] = ldo(C, ee);
         jv[k] = ldo(Dst, ee);
         if (BOX) uv[k] = ldo(g.U + ib, ee);
         if (HASW) iv[k] = ldo(g.IV + ib, ee);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < P2; ++k) {
+        const int e = lane + 64 * k;
+        av[k] = Val<VT>::cvt(ar[k]);
+        const R c = Val<VT>::cvt(cr[k]);
         const double lam = get_lam<CHECK, TAIL>(s, g, jv[k]);
         const double tk = -((double)c + (double)av[k] * lam);
         t[k] = e < d ? tk : -INFINITY;
