@@ -242,68 +242,103 @@ struct Obj {
 };
 
 // ---------------------------------------------------------------------------
-// LANE items: one lane per block, the block's d <= P values in registers
+// LANE items: one lane per block, the block's d <= P values in registers.
+// A group is handled in three steps: the loads of its stored values, the
+// t phase (gather lam, t in FP64) and the projection phase (threshold, x,
+// objective, per-destination sums).  Runs of groups of one size class are
+// software-pipelined: the loads of the next group are issued before the
+// projection phase of the current one, so a wave keeps memory busy while it
+// computes.
 // ---------------------------------------------------------------------------
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
-__device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, const Lds& s,
-                                           double gamma, Obj& ob)
+struct LaneGeo {
+    int64_t ib;   // stream offset of the group
+    int d, nb;    // rows (edges per block), blocks (lanes in use)
+};
+__device__ __forceinline__ LaneGeo lane_geo(const Item& it)
 {
-    static_assert(P <= 32, "lane blocks hold at most 32 edges");
+    LaneGeo q;
+    q.ib = uni64(it.base);
+    q.d = uni(it.d);
+    q.nb = uni(it.nb);
+    return q;
+}
+
+// stored values of rows k < P, as loaded
+template <typename VT, bool BOX, bool HASW, int P>
+struct LaneRaw {
+    VT a[P], c[P];
+    int j[P];
+    float u[BOX ? P : 1];
+    float w[HASW ? P : 1];
+};
+
+// values the projection phase works on
+template <typename VT, bool CHECK, bool BOX, bool HASW, int P>
+struct LaneVals {
     using R = typename Val<VT>::reg;
-    const int lane = threadIdx.x & 63;
-    const int d = uni(it.d), nb = uni(it.nb);
-    const int64_t ib = uni64(it.base);
-    const bool act = lane < nb;
-    // idle lanes read the last block's addresses (same lines, no extra traffic);
-    // per-lane offsets are 32-bit from a wave-uniform base
-    const int lc = act ? lane : nb - 1;
-    const VT* __restrict__ A = (const VT*)g.A + ib;
-    const VT* __restrict__ C = (const VT*)g.C + ib;
-    const int32_t* __restrict__ Dst = g.dst + ib;
-    const float* __restrict__ U = BOX ? g.U + ib : nullptr;
-    const float* __restrict__ IV = HASW ? g.IV + ib : nullptr;
-    const double inv_g = 1.0 / gamma;
-
     double t[P];
-    R av[P];
-    R cv[CHECK ? P : 1];
-    int jv[P];
-    float uv[BOX ? P : 1];
-    float iv[HASW ? P : 1];
+    R a[P];
+    R c[CHECK ? P : 1];
+    int j[P];
+    float u[BOX ? P : 1];
+    float w[HASW ? P : 1];
+};
 
-    // pass 1: loads (rows beyond d re-read row d-1, so every load is
-    // unconditional), then t in FP64.  The loads of a tile of up to 16 rows
-    // are all issued before the first use, behind a scheduling fence: left
-    // to itself the scheduler interleaves each row's loads with its use and
-    // the wave pays one memory round trip per row instead of one per tile.
-    constexpr int T = P < 16 ? P : 16;
+// loads of rows [K0, K1) (rows beyond d re-read row d-1 and idle lanes read
+// the last block, so every load is unconditional and in bounds; offsets are
+// 32-bit from a wave-uniform base)
+template <int K0, int K1, typename VT, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_load(const GradArgs& g, const LaneGeo& q, LaneRaw<VT, BOX, HASW, P>& r)
+{
+    const int lane = threadIdx.x & 63;
+    const int lc = lane < q.nb ? lane : q.nb - 1;
+    const VT* __restrict__ A = (const VT*)g.A + q.ib;
+    const VT* __restrict__ C = (const VT*)g.C + q.ib;
+    const int32_t* __restrict__ Dst = g.dst + q.ib;
 #pragma unroll
-    for (int k0 = 0; k0 < P; k0 += T) {
-        VT ar[T], cr[T];
-#pragma unroll
-        for (int k = k0; k < k0 + T && k < P; ++k) {
-            const int kk = k < d ? k : d - 1;
-            const uint32_t off = (uint32_t)(lc + kk * nb);
-            ar[k - k0] = ldo(A, off);
-            cr[k - k0] = ldo(C, off);
-            jv[k] = ldo(Dst, off);
-            if (BOX) uv[k] = ldo(U, off);
-            if (HASW) iv[k] = ldo(IV, off);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = k0; k < k0 + T && k < P; ++k) {
-            av[k] = Val<VT>::cvt(ar[k - k0]);
-            const R c = Val<VT>::cvt(cr[k - k0]);
-            const double lam = get_lam<CHECK, TAIL>(s, g, jv[k]);
-            const double tk = -((double)c + (double)av[k] * lam);
-            t[k] = (k < d && act) ? tk : -INFINITY;
-            if (CHECK) cv[k] = c;
-        }
-        __builtin_amdgcn_sched_barrier(0);
+    for (int k = K0; k < K1; ++k) {
+        const int kk = k < q.d ? k : q.d - 1;
+        const uint32_t off = (uint32_t)(lc + kk * q.nb);
+        r.a[k] = ldo(A, off);
+        r.c[k] = ldo(C, off);
+        r.j[k] = ldo(Dst, off);
+        if (BOX) r.u[k] = ldo(g.U + q.ib, off);
+        if (HASW) r.w[k] = ldo(g.IV + q.ib, off);
     }
+}
 
-    // pass 2: simplex threshold in registers
+// t phase of rows [K0, K1): t_e = -(c_e + a_e lam_j(e)) in FP64; rows beyond
+// d and idle lanes get t = -inf (never active)
+template <int K0, int K1, typename VT, bool CHECK, bool TAIL, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_t(const GradArgs& g, const Lds& s, const LaneGeo& q,
+                                       const LaneRaw<VT, BOX, HASW, P>& r,
+                                       LaneVals<VT, CHECK, BOX, HASW, P>& v)
+{
+    using R = typename Val<VT>::reg;
+    const bool act = (int)(threadIdx.x & 63) < q.nb;
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        v.a[k] = Val<VT>::cvt(r.a[k]);
+        const R c = Val<VT>::cvt(r.c[k]);
+        v.j[k] = r.j[k];
+        if (BOX) v.u[k] = r.u[k];
+        if (HASW) v.w[k] = r.w[k];
+        const double lam = get_lam<CHECK, TAIL>(s, g, v.j[k]);
+        const double tk = -((double)c + (double)v.a[k] * lam);
+        v.t[k] = (k < q.d && act) ? tk : -INFINITY;
+        if (CHECK) v.c[k] = c;
+    }
+}
+
+// projection phase: simplex threshold in registers, then x, the objective
+// and the per-destination sums
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+__device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, const LaneGeo& q,
+                                             double gamma, Obj& ob, const LaneVals<VT, CHECK, BOX, HASW, P>& v)
+{
+    const int d = q.d;
+    const double inv_g = 1.0 / gamma;
+    const double* t = v.t;
     double tau = 0.0;
     if (!BOX && !HASW) {
         // uniform weight w = 1/gamma: sum max(0, w t) > 1  <=>  sum max(0, t) > gamma,
@@ -345,8 +380,8 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
         double s0 = 0.0, mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const double w = (double)iv[HASW ? k : 0] * inv_g;
-            const double iw = gamma / (double)iv[HASW ? k : 0];
+            const double w = (double)v.w[HASW ? k : 0] * inv_g;
+            const double iw = gamma / (double)v.w[HASW ? k : 0];
             const double z = w * t[k];
             s0 += z > 0.0 ? z : 0.0;
             const double lo = t[k] - iw;
@@ -358,7 +393,7 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
             int n = 0;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const double w = (double)iv[HASW ? k : 0] * inv_g;
+                const double w = (double)v.w[HASW ? k : 0] * inv_g;
                 const bool in = t[k] > tau;
                 sw += in ? w : 0.0;
                 swt += in ? w * t[k] : 0.0;
@@ -371,7 +406,7 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
                 int n2 = 0;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    const double w = (double)iv[HASW ? k : 0] * inv_g;
+                    const double w = (double)v.w[HASW ? k : 0] * inv_g;
                     const bool in = t[k] > tn;
                     sw2 += in ? w : 0.0;
                     swt2 += in ? w * t[k] : 0.0;
@@ -386,20 +421,20 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
         }
     }
 
-    // pass 3: x, objective, per-destination sums of the LDS-resident rows
+    // x, objective, per-destination sums of the LDS-resident rows
     bool tail = false;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         if (k < d) {
-            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-            const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+            const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+            const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
             if (x != 0.0) {
-                const double q2 = HASW ? x * x / (double)iv[k] : x * x;
+                const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
                 ob.ot += t[k] * x;
                 ob.oq += q2;
-                const double cx = CHECK ? (double)cv[k] * x : 0.0;
+                const double cx = CHECK ? (double)v.c[k] * x : 0.0;
                 if (CHECK) ob.oc += cx;
-                if (!TAIL || jv[k] < g.K) accum_lds<CHECK>(s, jv[k], (double)opq(av[k]) * x, cx, q2);
+                if (!TAIL || v.j[k] < g.K) accum_lds<CHECK>(s, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
                 else tail = true;
             }
         }
@@ -409,24 +444,126 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if (k < d) {
-                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-                const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
-                if (x != 0.0 && jv[k] >= g.K) {
-                    const double q2 = HASW ? x * x / (double)iv[k] : x * x;
-                    accum_tail<CHECK>(g, jv[k], (double)opq(av[k]) * x, CHECK ? (double)opq(cv[k]) * x : 0.0, q2);
+                const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+                const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
+                if (x != 0.0 && v.j[k] >= g.K) {
+                    const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
+                    accum_tail<CHECK>(g, v.j[k], (double)opq(v.a[k]) * x,
+                                      CHECK ? (double)opq(v.c[k]) * x : 0.0, q2);
                 }
             }
         }
     }
     if (g.X) {
+        const int lane = threadIdx.x & 63;
+        if (lane < q.nb) {
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (k < d && act) {
-                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-                g.X[g.perm[ib + lc + k * nb]] = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+            for (int k = 0; k < P; ++k) {
+                if (k < d) {
+                    const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+                    g.X[g.perm[q.ib + lane + (int64_t)k * q.nb]] = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
+                }
             }
         }
     }
+}
+
+// one group of up to 32 rows, not pipelined: the loads go out in tiles of up
+// to 16 rows, each tile's loads all issued before their first use behind a
+// scheduling fence (left to itself the scheduler interleaves each row's loads
+// with its use, one memory round trip per row)
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+__device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, const Lds& s,
+                                           double gamma, Obj& ob)
+{
+    static_assert(P <= 32, "lane blocks hold at most 32 edges");
+    const LaneGeo q = lane_geo(it);
+    LaneRaw<VT, BOX, HASW, P> r;
+    LaneVals<VT, CHECK, BOX, HASW, P> v;
+    constexpr int T = P < 16 ? P : 16;
+    lane_load<0, T>(g, q, r);
+    __builtin_amdgcn_sched_barrier(0);
+    lane_t<0, T, VT, CHECK, TAIL>(g, s, q, r, v);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (P > T) {
+        lane_load<T, P>(g, q, r);
+        __builtin_amdgcn_sched_barrier(0);
+        lane_t<T, P, VT, CHECK, TAIL>(g, s, q, r, v);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    lane_project<VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
+}
+
+// size class of a lane block of d edges (FP64 storage: at most 8)
+template <typename VT>
+__device__ __forceinline__ int lane_class(int d)
+{
+    if (sizeof(VT) == 8) return d <= 4 ? 4 : 8;
+    return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : d <= 16 ? 16 : d <= 24 ? 24 : 32;
+}
+
+// item r of a batch of 64 descriptors held one per lane
+__device__ __forceinline__ Item item_at(const Item& mine, int r)
+{
+    Item it;
+    it.base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine.base >> 32), r) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)mine.base, r));
+    it.d = __builtin_amdgcn_readlane(mine.d, r);
+    const int nbk = __builtin_amdgcn_readlane((int)mine.nb | ((int)mine.kind << 16) | ((int)mine.proj << 24), r);
+    it.nb = (uint16_t)(nbk & 0xFFFF);
+    it.kind = (uint8_t)((nbk >> 16) & 0xFF);
+    it.proj = (uint8_t)((nbk >> 24) & 0xFF);
+    return it;
+}
+
+// a run of lane groups of one size class P <= 16 starting at batch entry r:
+// the next group's loads are in flight while the current group projects.
+// Ordinary passes (lam from LDS) issue them before the t phase; passes that
+// gather lam from global memory issue them after it, so that waiting for the
+// lam loads never waits for the prefetch as well.  Returns the first entry
+// not processed.
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+__device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int r, const int rn, const Lds& s,
+                                        double gamma, Obj& ob)
+{
+    static_assert(P <= 16, "pipelined lane runs hold at most 16 rows per group");
+    constexpr bool EARLY = !CHECK && !TAIL;
+    LaneGeo q = lane_geo(item_at(mine, r));
+    LaneRaw<VT, BOX, HASW, P> cur;
+    lane_load<0, P>(g, q, cur);
+#pragma unroll 1
+    for (;;) {
+        // the next group of this class, else the current one again (its
+        // loads are in bounds and their values are never used)
+        bool more = false;
+        LaneGeo qn = q;
+        if (r + 1 < rn) {
+            const Item nx = item_at(mine, r + 1);
+            if ((nx.proj == 1) == BOX && nx.kind == 0 && lane_class<VT>(nx.d) == P) {
+                more = true;
+                qn = lane_geo(nx);
+            }
+        }
+        LaneRaw<VT, BOX, HASW, P> nxt;
+        LaneVals<VT, CHECK, BOX, HASW, P> v;
+        __builtin_amdgcn_sched_barrier(0);
+        if (EARLY) {
+            lane_load<0, P>(g, qn, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+            lane_t<0, P, VT, CHECK, TAIL>(g, s, q, cur, v);
+        } else {
+            lane_t<0, P, VT, CHECK, TAIL>(g, s, q, cur, v);
+            __builtin_amdgcn_sched_barrier(0);
+            lane_load<0, P>(g, qn, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        lane_project<VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
+        if (!more) break;
+        cur = nxt;
+        q = qn;
+        ++r;
+    }
+    return r + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -704,19 +841,20 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
 // ---------------------------------------------------------------------------
 // the fused gradient kernel: one workgroup per chunk
 // ---------------------------------------------------------------------------
+// lane groups from batch entry r on; returns the first entry not processed
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
-__device__ __forceinline__ void lane_dispatch(const GradArgs& g, const Item& it, const Lds& s,
-                                              double gamma, Obj& ob)
+__device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine, const int r, const int rn,
+                                             const Item& it, const Lds& s, double gamma, Obj& ob)
 {
     // FP64 storage keeps blocks of at most 8 edges in lanes (register budget)
-    constexpr bool W8 = sizeof(VT) == 8;
-    const int d = it.d;
-    if (d <= 4) lane_group<VT, CHECK, HASW, TAIL, BOX, 4>(g, it, s, gamma, ob);
-    else if (d <= 8 || W8) lane_group<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
-    else if (d <= 12) lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, it, s, gamma, ob);
-    else if (d <= 16) lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, it, s, gamma, ob);
-    else if (d <= 24) lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 24>(g, it, s, gamma, ob);
-    else lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 32>(g, it, s, gamma, ob);
+    switch (lane_class<VT>(it.d)) {
+    case 4: return lane_run<VT, CHECK, HASW, TAIL, BOX, 4>(g, mine, r, rn, s, gamma, ob);
+    case 8: return lane_run<VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
+    case 12: return lane_run<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
+    case 16: return lane_run<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
+    case 24: lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 24>(g, it, s, gamma, ob); return r + 1;
+    default: lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 32>(g, it, s, gamma, ob); return r + 1;
+    }
 }
 
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
@@ -782,21 +920,15 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             Item mine = {0, 0, 0, 0, 0};
             if (r0 + lane < nmine) mine = g.items[my];
             const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
-            for (int r = 0; r < rn; ++r) {
-                Item it;
-                it.base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine.base >> 32), r) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)mine.base, r));
-                it.d = __builtin_amdgcn_readlane(mine.d, r);
-                const int nbk = __builtin_amdgcn_readlane((int)mine.nb | ((int)mine.kind << 16) | ((int)mine.proj << 24), r);
-                it.nb = (uint16_t)(nbk & 0xFFFF);
-                it.kind = (uint8_t)((nbk >> 16) & 0xFF);
-                it.proj = (uint8_t)((nbk >> 24) & 0xFF);
+            for (int r = 0; r < rn;) {
+                const Item it = item_at(mine, r);
                 if (kind == 0) {
-                    if (it.proj == 1) lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-                    else lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+                    if (it.proj == 1) r = lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, mine, r, rn, it, s, gamma, ob);
+                    else r = lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, mine, r, rn, it, s, gamma, ob);
                 } else {
                     if (it.proj == 1) wave_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
                     else wave_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+                    ++r;
                 }
             }
         }
