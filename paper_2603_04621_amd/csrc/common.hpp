@@ -60,6 +60,9 @@ struct SolveState {
     int64_t k, ks;
     int32_t stage, done, converged, status;
     int32_t stage_eval, pad;
+    // the step the scalar kernel chose for the row kernel
+    double step_eta, step_beta;
+    int32_t step_adv, step_stop;
 };
 
 // Constant parameters of a solve (kernel argument).

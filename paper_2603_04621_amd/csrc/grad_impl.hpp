@@ -421,36 +421,33 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
         }
     }
 
-    // x, objective, per-destination sums of the LDS-resident rows
+    // x, objective, per-destination sums of the LDS-resident rows (rows
+    // beyond d and idle lanes have t = -inf, hence x = 0, and are skipped)
     bool tail = false;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-        if (k < d) {
-            const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
-            const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
-            if (x != 0.0) {
-                const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
-                ob.ot += t[k] * x;
-                ob.oq += q2;
-                const double cx = CHECK ? (double)v.c[k] * x : 0.0;
-                if (CHECK) ob.oc += cx;
-                if (!TAIL || v.j[k] < g.K) accum_lds<CHECK>(s, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
-                else tail = true;
-            }
+        const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+        const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
+        if (x != 0.0) {
+            const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
+            ob.ot += t[k] * x;
+            ob.oq += q2;
+            const double cx = CHECK ? (double)v.c[k] * x : 0.0;
+            if (CHECK) ob.oc += cx;
+            if (!TAIL || v.j[k] < g.K) accum_lds<CHECK>(s, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
+            else tail = true;
         }
     }
     // rows beyond K (only when some lane of the wave has one)
     if (TAIL && __builtin_amdgcn_ballot_w64(tail)) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            if (k < d) {
-                const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
-                const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
-                if (x != 0.0 && v.j[k] >= g.K) {
-                    const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
-                    accum_tail<CHECK>(g, v.j[k], (double)opq(v.a[k]) * x,
-                                      CHECK ? (double)opq(v.c[k]) * x : 0.0, q2);
-                }
+            const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+            const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
+            if (x != 0.0 && v.j[k] >= g.K) {
+                const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
+                accum_tail<CHECK>(g, v.j[k], (double)opq(v.a[k]) * x, CHECK ? (double)opq(v.c[k]) * x : 0.0,
+                                  q2);
             }
         }
     }
@@ -892,12 +889,25 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
         s.hq = (float*)p;
     }
     const double gamma = g.gamma_ptr ? *g.gamma_ptr : g.gamma_val;
-    for (int j = threadIdx.x; j < K; j += kWG) {
-        if (!CHECK) s.lam[j] = g.lam[j];
-        s.hg[j] = 0.0f;
-        if (CHECK) {
-            s.hc[j] = 0.0f;
-            s.hq[j] = 0.0f;
+    // LDS rows: lam (8 rows per thread in flight at once) and zeroed sums
+    {
+        int j = threadIdx.x;
+        if (!CHECK) {
+            for (; j + 7 * kWG < K; j += 8 * kWG) {
+                double l[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) l[u] = g.lam[j + u * kWG];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s.lam[j + u * kWG] = l[u];
+            }
+            for (; j < K; j += kWG) s.lam[j] = g.lam[j];
+        }
+        for (j = threadIdx.x; j < K; j += kWG) {
+            s.hg[j] = 0.0f;
+            if (CHECK) {
+                s.hc[j] = 0.0f;
+                s.hq[j] = 0.0f;
+            }
         }
     }
     __syncthreads();

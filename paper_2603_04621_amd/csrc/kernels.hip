@@ -92,10 +92,16 @@ hipError_t set_grad_attributes(size_t lds)
 // ---------------------------------------------------------------------------
 // per-destination combination of the chunk partials (fixed order)
 // ---------------------------------------------------------------------------
+// a workgroup takes 64 rows; each row's chunk partials are split into
+// kRedSlices slices read by separate waves (all loads of a slice in flight
+// together), then combined in slice order
+constexpr int kRedSlices = 16;
+constexpr int kRedThreads = 64 * kRedSlices;
+
 __device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
 {
     if (r.done && *r.done) return;
-    __shared__ double sh[3][4][64];
+    __shared__ double sh[3][kRedSlices][64];
     const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int j = blk * 64 + l;
     const int planes = r.check ? 3 : 1;
@@ -103,16 +109,23 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
     for (int p = 0; p < planes; ++p) {
         double acc = 0.0;
         if (j < r.K) {
-            const int c0 = (int)(((int64_t)r.nchunks * q) / 4);
-            const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / 4);
+            const int c0 = (int)(((int64_t)r.nchunks * q) / kRedSlices);
+            const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / kRedSlices);
             const float* col = r.part + p * plane + j;
             int c = c0;
-            for (; c + 8 <= c1; c += 8) {
-                float v[8];
+            for (; c + 16 <= c1; c += 16) {
+                float v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)(c + u) * r.K];
+                for (int u = 0; u < 16; ++u) v[u] = col[(int64_t)(c + u) * r.K];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc += (double)v[u];
+                for (int u = 0; u < 16; ++u) acc += (double)v[u];
+            }
+            for (; c + 4 <= c1; c += 4) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = col[(int64_t)(c + u) * r.K];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc += (double)v[u];
             }
             for (; c < c1; ++c) acc += (double)col[(int64_t)c * r.K];
         }
@@ -123,12 +136,14 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
     double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (j < r.J) {
         const double gamma = r.gamma_ptr ? *r.gamma_ptr : r.gamma_val;
-        double ax, cj = 0.0, qj = 0.0;
+        double ax = 0.0, cj = 0.0, qj = 0.0;
         if (j < r.K) {
-            ax = ((sh[0][0][l] + sh[0][1][l]) + sh[0][2][l]) + sh[0][3][l];
+            for (int i = 0; i < kRedSlices; ++i) ax += sh[0][i][l];
             if (r.check) {
-                cj = ((sh[1][0][l] + sh[1][1][l]) + sh[1][2][l]) + sh[1][3][l];
-                qj = ((sh[2][0][l] + sh[2][1][l]) + sh[2][2][l]) + sh[2][3][l];
+                for (int i = 0; i < kRedSlices; ++i) {
+                    cj += sh[1][i][l];
+                    qj += sh[2][i][l];
+                }
             }
         } else {
             ax = r.tail[j];
@@ -168,10 +183,10 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
     }
 }
 
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) { reduce_body(r, blockIdx.x); }
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs r) { reduce_body(r, blockIdx.x); }
 
 // batched form: block b reduces row block rt[b].y of problem rt[b].x
-__global__ __launch_bounds__(256) void reduce_kernel_batch(const ReduceArgs* __restrict__ tab,
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel_batch(const ReduceArgs* __restrict__ tab,
                                                            const int2* __restrict__ rt)
 {
     const int2 e = rt[blockIdx.x];
@@ -181,13 +196,13 @@ __global__ __launch_bounds__(256) void reduce_kernel_batch(const ReduceArgs* __r
 
 hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3(nblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(reduce_kernel, dim3(nblk), dim3(kRedThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_batch(const ReduceArgs* tab, const int2* rt, int nblocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_kernel_batch, dim3(nblocks), dim3(256), 0, s, tab, rt);
+    hipLaunchKernelGGL(reduce_kernel_batch, dim3(nblocks), dim3(kRedThreads), 0, s, tab, rt);
     return hipGetLastError();
 }
 
@@ -268,13 +283,14 @@ hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double*
 // accelerated ascent step (one workgroup): scalars, step size, stop test,
 // gamma stage, projected step and momentum on lam'
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void agd_body(const AgdArgs& a)
+// scalar half of the step (all threads of one workgroup): the reduced
+// scalars, the step size, the stop test and the stage logic; sc receives
+// eta, beta, advance, stop (shared memory)
+__device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
 {
     SolveState* st = a.st;
-    if (st->done) return;
     __shared__ double red[9 * kSW];
     __shared__ double v[9];
-    __shared__ double sc[4];   // eta, beta, advance, stop
     reduce_scalars(a.obj_part, a.nchunks, a.blockpart, a.nblk, v, red);
     const SolveParams& P = a.prm;
     if (threadIdx.x == 0) {
@@ -359,41 +375,80 @@ __device__ __forceinline__ void agd_body(const AgdArgs& a)
         sc[3] = stop;
     }
     __syncthreads();
-    if (sc[3] != 0.0) return;
-    const double eta = sc[0], beta = sc[1];
-    const bool adv = sc[2] != 0.0;
-    for (int j = threadIdx.x; j < a.J; j += blockDim.x) {
-        const double yj = a.y[j], Gj = a.G[j];
+}
+
+// row half of the step: projected ascent step and momentum on rows
+// j0, j0 + stride, ...
+__device__ __forceinline__ void agd_rows(const AgdArgs& a, const double eta, const double beta, const bool adv,
+                                         const int j0, const int stride)
+{
+    for (int j = j0; j < a.J; j += stride) {
+        const double yj = a.y[j], Gj = a.G[j], lj = a.lam[j], Dj = a.D[j];
         double ln = yj + eta * Gj;
         ln = ln > 0.0 ? ln : 0.0;
-        a.yp[j] = yj;
-        a.Gp[j] = Gj;
         double yn;
         if (adv) {
             yn = ln;
         } else {
-            const double z = ln + beta * (ln - a.lam[j]);
+            const double z = ln + beta * (ln - lj);
             yn = z > 0.0 ? z : 0.0;
         }
+        a.yp[j] = yj;
+        a.Gp[j] = Gj;
         a.lam[j] = ln;
         a.y[j] = yn;
-        a.lam_eval[j] = a.D[j] * yn;
+        a.lam_eval[j] = Dj * yn;
     }
 }
 
-__global__ __launch_bounds__(kScalarThreads) void agd_kernel(AgdArgs a) { agd_body(a); }
-
-// batched form: workgroup b steps problem b
-__global__ __launch_bounds__(kScalarThreads) void agd_kernel_batch(const AgdArgs* __restrict__ tab)
+// single problem: the scalar kernel (one workgroup) leaves the step in the
+// solve state, the row kernel applies it with one thread per row
+__global__ __launch_bounds__(kScalarThreads) void agd_scalar_kernel(AgdArgs a)
 {
-    const AgdArgs a = tab[blockIdx.x];
-    agd_body(a);
+    SolveState* st = a.st;
+    __shared__ double sc[4];
+    if (st->done) {
+        if (threadIdx.x == 0) st->step_stop = 1;
+        return;
+    }
+    agd_scalars(a, sc);
+    if (threadIdx.x == 0) {
+        st->step_eta = sc[0];
+        st->step_beta = sc[1];
+        st->step_adv = sc[2] != 0.0 ? 1 : 0;
+        st->step_stop = sc[3] != 0.0 ? 1 : 0;
+    }
+}
+
+constexpr int kRowThreads = 256;
+
+__global__ __launch_bounds__(kRowThreads) void agd_row_kernel(AgdArgs a)
+{
+    const SolveState* st = a.st;
+    if (st->step_stop) return;
+    agd_rows(a, st->step_eta, st->step_beta, st->step_adv != 0, blockIdx.x * kRowThreads + threadIdx.x,
+             gridDim.x * kRowThreads);
 }
 
 hipError_t launch_agd(const AgdArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(agd_kernel, dim3(1), dim3(kScalarThreads), 0, s, a);
+    hipLaunchKernelGGL(agd_scalar_kernel, dim3(1), dim3(kScalarThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nb = a.J > 0 ? (a.J + kRowThreads - 1) / kRowThreads : 1;
+    hipLaunchKernelGGL(agd_row_kernel, dim3(nb), dim3(kRowThreads), 0, s, a);
     return hipGetLastError();
+}
+
+// batched form: workgroup b steps problem b (both halves in one workgroup)
+__global__ __launch_bounds__(kScalarThreads) void agd_kernel_batch(const AgdArgs* __restrict__ tab)
+{
+    const AgdArgs a = tab[blockIdx.x];
+    if (a.st->done) return;
+    __shared__ double sc[4];
+    agd_scalars(a, sc);
+    if (sc[3] != 0.0) return;
+    agd_rows(a, sc[0], sc[1], sc[2] != 0.0, threadIdx.x, blockDim.x);
 }
 
 hipError_t launch_agd_batch(const AgdArgs* tab, int count, hipStream_t s)
