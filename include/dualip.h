@@ -166,7 +166,9 @@ dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, double gamma, do
  *   graph_iters          iterations captured per hipGraph launch (0 = auto).
  *   time_kernels         1: launch eagerly (no graph) with HIP events around
  *                        every fused gradient launch on hip_stream; the mean
- *                        launch time is returned in grad_kernel_ms.
+ *                        launch times are returned in grad_kernel_ms
+ *                        (ordinary iterations) and check_kernel_ms (gap-check
+ *                        iterations).
  *   trace_host           NULL or [max_iters * DL_TRACE_W] FP64 rows:
  *                        g, rel_gap (NaN off-check), eta, gamma, stage, |G'|. */
 #define DL_TRACE_W 6
@@ -193,8 +195,11 @@ typedef struct {
     int64_t iters;           /* gradient evaluations performed                  */
     double gamma, g, P, rel_gap, max_infeas;   /* at the returned point        */
     double seconds;          /* wall time of the call                           */
-    double grad_kernel_ms;   /* mean fused-gradient launch time (time_kernels)  */
+    double grad_kernel_ms;   /* mean fused-gradient launch time of ordinary
+                                iterations (time_kernels)                       */
     int64_t grad_launches;   /* launches that time covers                       */
+    double check_kernel_ms;  /* the same for gap-check iterations               */
+    int64_t check_launches;
 } dl_solve_result;
 
 /* Runs the solve on hip_stream and waits for it.

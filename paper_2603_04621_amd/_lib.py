@@ -58,7 +58,8 @@ class SolveResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("converged", c_i32), ("stage", c_i32),
                 ("iters", c_i64), ("gamma", c_dbl), ("g", c_dbl), ("P", c_dbl),
                 ("rel_gap", c_dbl), ("max_infeas", c_dbl), ("seconds", c_dbl),
-                ("grad_kernel_ms", c_dbl), ("grad_launches", c_i64)]
+                ("grad_kernel_ms", c_dbl), ("grad_launches", c_i64),
+                ("check_kernel_ms", c_dbl), ("check_launches", c_i64)]
 
 
 class ProblemInfo(ctypes.Structure):

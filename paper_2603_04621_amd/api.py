@@ -120,12 +120,15 @@ class SolveOutcome:
     seconds: float
     grad_kernel_ms: float
     grad_launches: int
+    check_kernel_ms: float = 0.0
+    check_launches: int = 0
     trace: Optional[np.ndarray] = field(default=None, repr=False)
 
 
 def outcome(r: L.SolveResult, trace=None) -> SolveOutcome:
     return SolveOutcome(r.status, bool(r.converged), r.stage, r.iters, r.gamma, r.g, r.P,
                         r.rel_gap, r.max_infeas, r.seconds, r.grad_kernel_ms, r.grad_launches,
+                        r.check_kernel_ms, r.check_launches,
                         None if trace is None else trace[: r.iters])
 
 

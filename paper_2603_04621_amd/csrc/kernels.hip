@@ -430,8 +430,24 @@ __global__ __launch_bounds__(kRowThreads) void agd_row_kernel(AgdArgs a)
              gridDim.x * kRowThreads);
 }
 
+// small problems: both halves in one workgroup (one launch less per iteration)
+constexpr int kAgdFusedRows = 4096;
+
+__global__ __launch_bounds__(kScalarThreads) void agd_fused_kernel(AgdArgs a)
+{
+    if (a.st->done) return;
+    __shared__ double sc[4];
+    agd_scalars(a, sc);
+    if (sc[3] != 0.0) return;
+    agd_rows(a, sc[0], sc[1], sc[2] != 0.0, threadIdx.x, blockDim.x);
+}
+
 hipError_t launch_agd(const AgdArgs& a, hipStream_t s)
 {
+    if (a.J <= kAgdFusedRows) {
+        hipLaunchKernelGGL(agd_fused_kernel, dim3(1), dim3(kScalarThreads), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(agd_scalar_kernel, dim3(1), dim3(kScalarThreads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -72,8 +72,8 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
     int64_t seg = o->graph_iters > 0 ? o->graph_iters : (o->check_every > 0 ? o->check_every : 16);
     if (o->check_every > 0 && seg % o->check_every != 0) seg = o->check_every;
     int64_t k = 0;
-    double kernel_ms = 0.0;
-    int64_t launches = 0;
+    double kernel_ms = 0.0, check_ms = 0.0;   // ordinary and gap-check gradient launches
+    int64_t launches = 0, check_launches = 0;
     SolveState* hst = p->st_host;
 
     if (o->time_kernels) {
@@ -83,18 +83,26 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
         for (auto& e : cl.events) TRY(hipEventCreate(&e), "event");
         while (k < N) {
             const int64_t nb = std::min<int64_t>(W, N - k);
-            for (int64_t q = 0; q < nb; ++q, ++k)
-                TRY(dlh::enqueue_iteration(p, prm, dlh::is_check_iter(o, k) ? 1 : 0, cl.trace, s,
-                                           cl.events[2 * q], cl.events[2 * q + 1]),
+            std::vector<char> chk((size_t)nb);
+            for (int64_t q = 0; q < nb; ++q, ++k) {
+                chk[(size_t)q] = dlh::is_check_iter(o, k) ? 1 : 0;
+                TRY(dlh::enqueue_iteration(p, prm, chk[(size_t)q], cl.trace, s, cl.events[2 * q],
+                                           cl.events[2 * q + 1]),
                     "iteration");
+            }
             TRY(hipMemcpyAsync(hst, p->st, sizeof(SolveState), hipMemcpyDeviceToHost, s), "copy state");
             TRY(hipStreamSynchronize(s), "synchronize");
             for (int64_t q = 0; q < nb; ++q) {
                 float ms = 0.0f;
                 TRY(hipEventElapsedTime(&ms, cl.events[2 * q], cl.events[2 * q + 1]), "elapsed");
-                kernel_ms += ms;
+                if (chk[(size_t)q]) {
+                    check_ms += ms;
+                    ++check_launches;
+                } else {
+                    kernel_ms += ms;
+                    ++launches;
+                }
             }
-            launches += nb;
             if (hst->done) break;
         }
     } else {
@@ -150,6 +158,8 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
     out->max_infeas = fs.max_infeas;
     out->grad_kernel_ms = launches > 0 ? kernel_ms / (double)launches : 0.0;
     out->grad_launches = launches;
+    out->check_kernel_ms = check_launches > 0 ? check_ms / (double)check_launches : 0.0;
+    out->check_launches = check_launches;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (fs.status == 5) {
         set_error("non-finite dual objective at iteration %lld", (long long)fs.k);
