@@ -221,8 +221,11 @@ struct HostLayout {
     int64_t n_lane = 0, n_wave = 0, n_wg = 0;
 };
 
-// Groups blocks by (kind, projection, degree), assigns stream positions and
-// splits the work into nchunks ranges balanced by nonzeros.
+// Groups blocks by (kind, projection, degree), deals the work items of each
+// kind round-robin to the chunks (in degree order, so every chunk gets the
+// same mix of sizes and the same share of nonzeros: a chunk's time follows
+// its number of items as much as its nonzeros) and lays the stream out chunk
+// by chunk, so each workgroup reads one contiguous region per kind.
 static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, HostLayout& L)
 {
     const int64_t I = d->num_blocks;
@@ -239,65 +242,76 @@ static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, Hos
     }
     std::stable_sort(wave.begin(), wave.end(), [](auto& a, auto& b) { return a.first < b.first; });
     std::stable_sort(wgb.begin(), wgb.end(), [](auto& a, auto& b) { return a.first < b.first; });
-    int64_t pos = 0;
-    struct Src { int64_t item; std::vector<int64_t> blocks; };
-    std::vector<std::pair<int64_t, int64_t>> group_blocks;   // item -> [start, end) in gb
+
+    // items of each kind in (proj, degree) order; gb holds their blocks
+    struct Proto {
+        Item it;
+        int64_t g0;   // first block in gb
+    };
+    std::vector<Proto> kinds[3];
     std::vector<int64_t> gb;
     for (int pr = 0; pr < 2; ++pr)
         for (int deg = 1; deg <= kLaneMaxDeg; ++deg) {
             const auto& v = lane[(size_t)pr * (kLaneMaxDeg + 1) + deg];
             for (size_t s0 = 0; s0 < v.size(); s0 += 64) {
                 const int nb = (int)std::min<size_t>(64, v.size() - s0);
-                Item it;
-                it.base = pos;
-                it.d = deg;
-                it.nb = (uint16_t)nb;
-                it.kind = ITEM_LANE;
-                it.proj = (uint8_t)pr;
-                L.items.push_back(it);
-                group_blocks.push_back({(int64_t)gb.size(), (int64_t)gb.size() + nb});
+                Proto q;
+                q.it = Item{0, deg, (uint16_t)nb, (uint8_t)ITEM_LANE, (uint8_t)pr};
+                q.g0 = (int64_t)gb.size();
                 for (int l = 0; l < nb; ++l) gb.push_back(v[s0 + l]);
-                pos += (int64_t)nb * deg;
-                ++L.n_lane;
+                kinds[0].push_back(q);
             }
         }
     for (auto& kv : wave) {
         const int64_t i = kv.second;
-        Item it;
-        it.base = pos;
-        it.d = (int32_t)(d->block_off[i + 1] - d->block_off[i]);
-        it.nb = 1;
-        it.kind = ITEM_WAVE;
-        it.proj = d->block_proj[i];
-        L.items.push_back(it);
-        group_blocks.push_back({(int64_t)gb.size(), (int64_t)gb.size() + 1});
+        Proto q;
+        q.it = Item{0, (int32_t)(d->block_off[i + 1] - d->block_off[i]), 1, (uint8_t)ITEM_WAVE, d->block_proj[i]};
+        q.g0 = (int64_t)gb.size();
         gb.push_back(i);
-        pos += it.d;
-        ++L.n_wave;
+        kinds[1].push_back(q);
     }
-    L.nA = (int64_t)L.items.size();
     for (auto& kv : wgb) {
         const int64_t i = kv.second;
-        Item it;
-        it.base = pos;
-        it.d = (int32_t)(d->block_off[i + 1] - d->block_off[i]);
-        it.nb = 1;
-        it.kind = ITEM_WG;
-        it.proj = d->block_proj[i];
-        L.items.push_back(it);
-        group_blocks.push_back({(int64_t)gb.size(), (int64_t)gb.size() + 1});
+        Proto q;
+        q.it = Item{0, (int32_t)(d->block_off[i + 1] - d->block_off[i]), 1, (uint8_t)ITEM_WG, d->block_proj[i]};
+        q.g0 = (int64_t)gb.size();
         gb.push_back(i);
-        pos += it.d;
-        ++L.n_wg;
+        kinds[2].push_back(q);
+    }
+    L.n_lane = (int64_t)kinds[0].size();
+    L.n_wave = (int64_t)kinds[1].size();
+    L.n_wg = (int64_t)kinds[2].size();
+
+    // deal: chunk c takes items c, c + nchunks, ... of each kind; stream
+    // positions follow the final item order
+    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0, 0, 0});
+    std::vector<int64_t> g0s;
+    int64_t pos = 0;
+    for (int k = 0; k < 3; ++k) {
+        const auto& v = kinds[k];
+        for (int c = 0; c < nchunks; ++c) {
+            int32_t* r = k == 0 ? &L.chunks[c].a0 : (k == 1 ? &L.chunks[c].w0 : &L.chunks[c].b0);
+            r[0] = (int32_t)L.items.size();
+            for (size_t q = (size_t)c; q < v.size(); q += (size_t)nchunks) {
+                Item it = v[q].it;
+                it.base = pos;
+                pos += (int64_t)it.d * it.nb;
+                L.items.push_back(it);
+                g0s.push_back(v[q].g0);
+            }
+            r[1] = (int32_t)L.items.size();
+        }
+        if (k == 1) L.nA = (int64_t)L.items.size();
     }
     L.nB = (int64_t)L.items.size() - L.nA;
+
     // stream position -> original column
     L.src.assign((size_t)pos, 0);
     const int64_t nit = (int64_t)L.items.size();
     parallel_for(nit, 4096, [&](int64_t lo, int64_t hi) {
         for (int64_t q = lo; q < hi; ++q) {
             const Item& it = L.items[q];
-            const int64_t g0 = group_blocks[q].first;
+            const int64_t g0 = g0s[q];
             if (it.kind == ITEM_LANE) {
                 for (int l = 0; l < it.nb; ++l) {
                     const int64_t c0 = d->block_off[gb[g0 + l]];
@@ -309,26 +323,6 @@ static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, Hos
             }
         }
     });
-    // chunks: each kind's list split evenly by nonzeros
-    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0, 0, 0});
-    auto split = [&](int64_t first, int64_t count, int which) {
-        std::vector<int64_t> pre((size_t)count + 1, 0);
-        for (int64_t q = 0; q < count; ++q)
-            pre[q + 1] = pre[q] + (int64_t)L.items[first + q].d * L.items[first + q].nb;
-        const int64_t tot = pre[count];
-        int64_t q = 0;
-        for (int c = 0; c < nchunks; ++c) {
-            const int64_t target = (int64_t)((double)tot * (c + 1) / nchunks);
-            const int64_t q0 = q;
-            while (q < count && (c == nchunks - 1 || pre[q] + (pre[q + 1] - pre[q]) / 2 < target)) ++q;
-            int32_t* r = which == 0 ? &L.chunks[c].a0 : (which == 1 ? &L.chunks[c].w0 : &L.chunks[c].b0);
-            r[0] = (int32_t)(first + q0);
-            r[1] = (int32_t)(first + q);
-        }
-    };
-    split(0, L.n_lane, 0);
-    split(L.n_lane, L.n_wave, 1);
-    split(L.nA, L.nB, 2);
 }
 
 static int device_cus(int dev)
