@@ -98,41 +98,10 @@ hipError_t set_grad_attributes(size_t lds)
 constexpr int kRedSlices = 16;
 constexpr int kRedThreads = 64 * kRedSlices;
 
-__device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
+// wave 0: per-row gradient and the block's scalar sums
+__device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk, const int l, const int j,
+                                              const double (*sh)[kRedSlices][64])
 {
-    if (r.done && *r.done) return;
-    __shared__ double sh[3][kRedSlices][64];
-    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int j = blk * 64 + l;
-    const int planes = r.check ? 3 : 1;
-    const int64_t plane = (int64_t)r.nchunks * r.K;
-    for (int p = 0; p < planes; ++p) {
-        double acc = 0.0;
-        if (j < r.K) {
-            const int c0 = (int)(((int64_t)r.nchunks * q) / kRedSlices);
-            const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / kRedSlices);
-            const float* col = r.part + p * plane + j;
-            int c = c0;
-            for (; c + 16 <= c1; c += 16) {
-                float v[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = col[(int64_t)(c + u) * r.K];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) acc += (double)v[u];
-            }
-            for (; c + 4 <= c1; c += 4) {
-                float v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = col[(int64_t)(c + u) * r.K];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc += (double)v[u];
-            }
-            for (; c < c1; ++c) acc += (double)col[(int64_t)c * r.K];
-        }
-        sh[p][q][l] = acc;
-    }
-    __syncthreads();
-    if (q != 0) return;
     double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (j < r.J) {
         const double gamma = r.gamma_ptr ? *r.gamma_ptr : r.gamma_val;
@@ -181,6 +150,49 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
 #pragma unroll
         for (int i = 0; i < 6; ++i) out[i] = S[i];
     }
+}
+
+// all threads of the workgroup return from it (the row part runs on wave 0)
+__device__ __forceinline__ void reduce_rows(const ReduceArgs& r, const int blk)
+{
+    __shared__ double sh[3][kRedSlices][64];
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int j = blk * 64 + l;
+    const int planes = r.check ? 3 : 1;
+    const int64_t plane = (int64_t)r.nchunks * r.K;
+    for (int p = 0; p < planes; ++p) {
+        double acc = 0.0;
+        if (j < r.K) {
+            const int c0 = (int)(((int64_t)r.nchunks * q) / kRedSlices);
+            const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / kRedSlices);
+            const float* col = r.part + p * plane + j;
+            int c = c0;
+            for (; c + 16 <= c1; c += 16) {
+                float v[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = col[(int64_t)(c + u) * r.K];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc += (double)v[u];
+            }
+            for (; c + 4 <= c1; c += 4) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = col[(int64_t)(c + u) * r.K];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc += (double)v[u];
+            }
+            for (; c < c1; ++c) acc += (double)col[(int64_t)c * r.K];
+        }
+        sh[p][q][l] = acc;
+    }
+    __syncthreads();
+    if (q == 0) reduce_finish(r, blk, l, j, sh);
+}
+
+__device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
+{
+    if (r.done && *r.done) return;
+    reduce_rows(r, blk);
 }
 
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs r) { reduce_body(r, blockIdx.x); }
@@ -378,27 +390,45 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
 }
 
 // row half of the step: projected ascent step and momentum on rows
-// j0, j0 + stride, ...
+// j0, j0 + stride, ... (four rows per thread in flight at once)
+__device__ __forceinline__ void agd_row(const AgdArgs& a, const int j, const double yj, const double Gj,
+                                        const double lj, const double Dj, const double eta, const double beta,
+                                        const bool adv)
+{
+    double ln = yj + eta * Gj;
+    ln = ln > 0.0 ? ln : 0.0;
+    double yn;
+    if (adv) {
+        yn = ln;
+    } else {
+        const double z = ln + beta * (ln - lj);
+        yn = z > 0.0 ? z : 0.0;
+    }
+    a.yp[j] = yj;
+    a.Gp[j] = Gj;
+    a.lam[j] = ln;
+    a.y[j] = yn;
+    a.lam_eval[j] = Dj * yn;
+}
+
 __device__ __forceinline__ void agd_rows(const AgdArgs& a, const double eta, const double beta, const bool adv,
                                          const int j0, const int stride)
 {
-    for (int j = j0; j < a.J; j += stride) {
-        const double yj = a.y[j], Gj = a.G[j], lj = a.lam[j], Dj = a.D[j];
-        double ln = yj + eta * Gj;
-        ln = ln > 0.0 ? ln : 0.0;
-        double yn;
-        if (adv) {
-            yn = ln;
-        } else {
-            const double z = ln + beta * (ln - lj);
-            yn = z > 0.0 ? z : 0.0;
+    int j = j0;
+    for (; j + 3 * stride < a.J; j += 4 * stride) {
+        double yv[4], gv[4], lv[4], dv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = j + u * stride;
+            yv[u] = a.y[i];
+            gv[u] = a.G[i];
+            lv[u] = a.lam[i];
+            dv[u] = a.D[i];
         }
-        a.yp[j] = yj;
-        a.Gp[j] = Gj;
-        a.lam[j] = ln;
-        a.y[j] = yn;
-        a.lam_eval[j] = Dj * yn;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) agd_row(a, j + u * stride, yv[u], gv[u], lv[u], dv[u], eta, beta, adv);
     }
+    for (; j < a.J; j += stride) agd_row(a, j, a.y[j], a.G[j], a.lam[j], a.D[j], eta, beta, adv);
 }
 
 // single problem: the scalar kernel (one workgroup) leaves the step in the
@@ -428,6 +458,54 @@ __global__ __launch_bounds__(kRowThreads) void agd_row_kernel(AgdArgs a)
     if (st->step_stop) return;
     agd_rows(a, st->step_eta, st->step_beta, st->step_adv != 0, blockIdx.x * kRowThreads + threadIdx.x,
              gridDim.x * kRowThreads);
+}
+
+// single problem: the reduction, and in the workgroup that finishes last the
+// scalar half of the step (and for J <= kStepRowsInReduce the row half too),
+// so an iteration is two or three launches.  Each workgroup fences its block
+// sums before it takes a ticket; the last one fences again before reading all
+// of them and resets the ticket for the next iteration.
+constexpr int kStepRowsInReduce = 16384;
+static_assert(kRedThreads == kScalarThreads, "the last reduction workgroup runs the scalar step");
+
+__global__ __launch_bounds__(kRedThreads) void reduce_step_kernel(ReduceArgs r, AgdArgs a, int32_t* ticket)
+{
+    SolveState* st = a.st;
+    if (st->done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->step_stop = 1;
+        return;
+    }
+    reduce_rows(r, blockIdx.x);
+    __threadfence();
+    __syncthreads();
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        const int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = t == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    __shared__ double sc[4];
+    agd_scalars(a, sc);
+    if (threadIdx.x == 0) {
+        st->step_eta = sc[0];
+        st->step_beta = sc[1];
+        st->step_adv = sc[2] != 0.0 ? 1 : 0;
+        st->step_stop = sc[3] != 0.0 ? 1 : 0;
+        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (a.J <= kStepRowsInReduce && sc[3] == 0.0) agd_rows(a, sc[0], sc[1], sc[2] != 0.0, threadIdx.x, blockDim.x);
+}
+
+hipError_t launch_reduce_step(const ReduceArgs& r, const AgdArgs& a, int32_t* ticket, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_step_kernel, dim3(nblk), dim3(kRedThreads), 0, s, r, a, ticket);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.J <= kStepRowsInReduce) return e;
+    const int nb = (a.J + kRowThreads - 1) / kRowThreads;
+    hipLaunchKernelGGL(agd_row_kernel, dim3(nb), dim3(kRowThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 // small problems: both halves in one workgroup (one launch less per iteration)

@@ -238,6 +238,29 @@ def test_solve_tiny_trajectory_fp64(O, dev, graph):
     assert lam_close(lam.cpu().numpy(), r_or.lam)
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_solve_trajectory_many_rows(O, dev, graph):
+    """J = 20,000 destinations: more rows than the reduction's last workgroup
+    steps itself (the separate row kernel runs) and than LDS holds (tail
+    rows); 300 iterations with a gap check every 10 follow the oracle's g
+    within 1e-6."""
+    from paper_2603_04621_amd.api import SolveSettings
+    inst = I.random_small(41, I=40_000, J=20_000, dmax=8, box_frac=0.2, capacity="greedy")
+    s = SolveSettings(gamma0=1e-2, gamma_final=1e-2, max_iters=300, check_every=10,
+                      tol_rel_gap=-1.0, max_step=1e-2, init_step=1e-4, trace=True,
+                      time_kernels=0 if graph else 1, graph_iters=20 if graph else 0)
+    r_or = O.solve(inst, oracle_opts(O, s))
+    with gpu_problem(inst, "f64") as p:
+        assert p.info()["lds_rows"] < inst.m
+        lam, r = p.solve(s)
+    assert r.iters == 300 == r_or.iters
+    tr_g, tr_o = r.trace[:, 0], r_or.trace[:, 0]
+    rel = np.abs(tr_g - tr_o) / np.maximum(1.0, np.abs(tr_o))
+    assert rel.max() <= 1e-6, (rel.max(), int(rel.argmax()))
+    assert abs(r.rel_gap - r_or.rel_gap) <= 1e-6
+    assert lam_close(lam.cpu().numpy(), r_or.lam)
+
+
 def test_solve_continuation_to_gap(O, dev):
     """gamma continuation with stage changes on the gap and on the iteration
     budget, stopping at rel_gap 1e-4; FP64 storage follows the oracle."""
