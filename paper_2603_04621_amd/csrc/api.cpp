@@ -516,7 +516,6 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     ALLOC(p->Gp, (size_t)m, "G_prev");
     ALLOC(p->lam_eval, (size_t)m, "lam_eval");
     ALLOC(p->st, 1, "state");
-    ALLOC(p->ticket, 1, "ticket");
     UP(p->A, Ah.data(), Ah.size(), "upload a");
     UP(p->C, Ch.data(), Ch.size(), "upload c");
     UP(p->dst, dsth.data(), dsth.size() * 4, "upload dst");
@@ -531,8 +530,6 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     {
         hipError_t e = hipMemsetAsync(p->tail, 0, (size_t)3 * m * sizeof(double), s);
         if (e != hipSuccess) { st = hip_fail(e, "clear tail"); free_problem(p); return st; }
-        e = hipMemsetAsync(p->ticket, 0, sizeof(int32_t), s);
-        if (e != hipSuccess) { st = hip_fail(e, "clear ticket"); free_problem(p); return st; }
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) { st = hip_fail(e, "upload"); free_problem(p); return st; }
         e = hipHostMalloc((void**)&p->st_host, 2 * sizeof(SolveState), hipHostMallocDefault);
@@ -667,7 +664,8 @@ hipError_t enqueue_iteration(dl_problem* p, const SolveParams& prm, int check, d
     if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
     ReduceArgs r = reduce_args(p, check, 0, p->lam_eval, gptr, 0.0, done, nullptr);
     AgdArgs a = agd_args(p, prm, check, trace);
-    return launch_reduce_step(r, a, p->ticket, p->nblk2, s);
+    if ((e = launch_reduce(r, p->nblk2, s)) != hipSuccess) return e;
+    return launch_agd(a, s);
 }
 
 dl_status check_solve_opts(const dl_solve_opts* o)

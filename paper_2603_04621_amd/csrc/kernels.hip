@@ -245,15 +245,16 @@ __device__ __forceinline__ void reduce_scalars(const double* obj_part, int nchun
     for (int k = 0; k < 8; ++k) v[k] = wave_sum(v[k]);
     v[8] = wave_max(v[8]);
     const int w = threadIdx.x >> 6;
+    const int nw = (int)(blockDim.x >> 6);
     if ((threadIdx.x & 63) == 0)
         for (int k = 0; k < 9; ++k) red[k * kSW + w] = v[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < 9; ++k) {
-            double a = 0.0;
-            for (int i = 0; i < kSW; ++i) a = k == 8 ? fmax(a, red[k * kSW + i]) : a + red[k * kSW + i];
-            out[k] = a;
-        }
+    // thread k combines scalar k over the waves, in wave order
+    if (threadIdx.x < 9) {
+        const int k = threadIdx.x;
+        double a = 0.0;
+        for (int i = 0; i < nw; ++i) a = k == 8 ? fmax(a, red[k * kSW + i]) : a + red[k * kSW + i];
+        out[k] = a;
     }
     __syncthreads();
 }
@@ -458,54 +459,6 @@ __global__ __launch_bounds__(kRowThreads) void agd_row_kernel(AgdArgs a)
     if (st->step_stop) return;
     agd_rows(a, st->step_eta, st->step_beta, st->step_adv != 0, blockIdx.x * kRowThreads + threadIdx.x,
              gridDim.x * kRowThreads);
-}
-
-// single problem: the reduction, and in the workgroup that finishes last the
-// scalar half of the step (and for J <= kStepRowsInReduce the row half too),
-// so an iteration is two or three launches.  Each workgroup fences its block
-// sums before it takes a ticket; the last one fences again before reading all
-// of them and resets the ticket for the next iteration.
-constexpr int kStepRowsInReduce = 16384;
-static_assert(kRedThreads == kScalarThreads, "the last reduction workgroup runs the scalar step");
-
-__global__ __launch_bounds__(kRedThreads) void reduce_step_kernel(ReduceArgs r, AgdArgs a, int32_t* ticket)
-{
-    SolveState* st = a.st;
-    if (st->done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->step_stop = 1;
-        return;
-    }
-    reduce_rows(r, blockIdx.x);
-    __threadfence();
-    __syncthreads();
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        const int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = t == (int)gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    __shared__ double sc[4];
-    agd_scalars(a, sc);
-    if (threadIdx.x == 0) {
-        st->step_eta = sc[0];
-        st->step_beta = sc[1];
-        st->step_adv = sc[2] != 0.0 ? 1 : 0;
-        st->step_stop = sc[3] != 0.0 ? 1 : 0;
-        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (a.J <= kStepRowsInReduce && sc[3] == 0.0) agd_rows(a, sc[0], sc[1], sc[2] != 0.0, threadIdx.x, blockDim.x);
-}
-
-hipError_t launch_reduce_step(const ReduceArgs& r, const AgdArgs& a, int32_t* ticket, int nblk, hipStream_t s)
-{
-    hipLaunchKernelGGL(reduce_step_kernel, dim3(nblk), dim3(kRedThreads), 0, s, r, a, ticket);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.J <= kStepRowsInReduce) return e;
-    const int nb = (a.J + kRowThreads - 1) / kRowThreads;
-    hipLaunchKernelGGL(agd_row_kernel, dim3(nb), dim3(kRowThreads), 0, s, a);
-    return hipGetLastError();
 }
 
 // small problems: both halves in one workgroup (one launch less per iteration)

@@ -74,8 +74,6 @@ size_t grad_lds_bytes(int K, bool check);
 hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s);
 hipError_t launch_agd(const AgdArgs& a, hipStream_t s);
-// reduction and ascent step of one solve iteration (ticket: device int, zero)
-hipError_t launch_reduce_step(const ReduceArgs& r, const AgdArgs& a, int32_t* ticket, int nblk, hipStream_t s);
 hipError_t launch_permute_in(const double* src, const int32_t* orig, int J, double* dst,
                              hipStream_t s);
 hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double* blockpart,

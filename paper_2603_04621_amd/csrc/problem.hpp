@@ -43,7 +43,6 @@ struct dl_problem {
     double *lam = nullptr, *y = nullptr, *yp = nullptr, *G = nullptr, *Gp = nullptr,
            *lam_eval = nullptr;
     dl::SolveState* st = nullptr;
-    int32_t* ticket = nullptr;           // last-workgroup counter of the reduction
     dl::SolveState* st_host = nullptr;   // pinned mirror (2 slots)
     std::vector<void*> allocs;
 };

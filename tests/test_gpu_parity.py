@@ -240,8 +240,8 @@ def test_solve_tiny_trajectory_fp64(O, dev, graph):
 
 @pytest.mark.parametrize("graph", [0, 1])
 def test_solve_trajectory_many_rows(O, dev, graph):
-    """J = 20,000 destinations: more rows than the reduction's last workgroup
-    steps itself (the separate row kernel runs) and than LDS holds (tail
+    """J = 20,000 destinations: more rows than one workgroup steps by itself
+    (the scalar-step and row-step kernels run) and than LDS holds (tail
     rows); 300 iterations with a gap check every 10 follow the oracle's g
     within 1e-6."""
     from paper_2603_04621_amd.api import SolveSettings
