@@ -74,21 +74,27 @@ def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0):
 
 
 def load_or_generate(I, args):
-    fields = ("dst", "a", "c", "b", "block_off", "block_proj")
-    tag = f"large_{args.sources}_{args.dests}"
+    fields = ("dst", "a", "c", "b", "block_off", "block_proj", "upper")
+    tag = f"{args.config}_{args.sources}_{args.dests}"
+    seed = I.SEED_BASE + (2 if args.config == "large" else 3)
     if args.cache:
         d = os.path.join(args.cache, tag)
-        if all(os.path.exists(os.path.join(d, f + ".npy")) for f in fields):
-            arr = {f: np.load(os.path.join(d, f + ".npy")) for f in fields}
+        if all(os.path.exists(os.path.join(d, f + ".npy")) for f in fields[:-1]):
+            arr = {f: np.load(os.path.join(d, f + ".npy")) for f in fields
+                   if os.path.exists(os.path.join(d, f + ".npy"))}
             return I.Instance(args.dests, int(arr["dst"].shape[0]), arr["dst"], arr["a"], arr["c"],
-                              arr["b"], arr["block_off"], arr["block_proj"], None, "large",
-                              I.SEED_BASE + 2)
-    inst = I.large(I=args.sources, J=args.dests)
+                              arr["b"], arr["block_off"], arr["block_proj"], arr.get("upper"),
+                              args.config, seed)
+    if args.config == "large":
+        inst = I.large(I=args.sources, J=args.dests)
+    else:
+        inst = I.heavy(I=args.sources, J=args.dests)
     if args.cache:
         d = os.path.join(args.cache, tag)
         os.makedirs(d, exist_ok=True)
         for f in fields:
-            np.save(os.path.join(d, f + ".npy"), getattr(inst, f))
+            if getattr(inst, f) is not None:
+                np.save(os.path.join(d, f + ".npy"), getattr(inst, f))
     return inst
 
 
@@ -211,8 +217,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--sources", type=int, default=10_000_000)
-    ap.add_argument("--dests", type=int, default=10_000)
+    ap.add_argument("--config", default="large", choices=["large", "heavy"],
+                    help="large: 10M sources, 10k destinations, Poisson degrees (the headline); "
+                         "heavy: 2M sources, 50k destinations, Pareto degrees, 30%% box blocks")
+    ap.add_argument("--sources", type=int, default=None)
+    ap.add_argument("--dests", type=int, default=None)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-binding", action="store_true",
@@ -232,6 +241,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
+    if args.sources is None:
+        args.sources = 10_000_000 if args.config == "large" else 2_000_000
+    if args.dests is None:
+        args.dests = 10_000 if args.config == "large" else 50_000
     if args.copy_calibration:
         import torch
         torch.cuda.set_device(0)
@@ -285,10 +298,21 @@ def main():
     ips = args.steps / el
     bytes_per = info["stream_bytes"]
     achieved = bytes_per / (r.grad_kernel_ms * 1e-3) / 1e9
-    wl = f"large I={args.sources} J={args.dests} {args.storage}"
+    wl = f"{args.config} I={args.sources} J={args.dests} {args.storage}"
     traffic = measured_traffic(wl)
+    if args.config == "large":
+        metric = "dual-ascent iter/s at 100M nnz (matching LP, FP32-stored a and c)"
+        workload = ("matching LP: I=%d sources, J=%d destinations, degree 1+Poisson(9), Zipf(1.1) "
+                    "destinations, simplex blocks, gamma=1e-3, gap test every %d iterations" %
+                    (args.sources, args.dests, args.check_every))
+    else:
+        metric = "dual-ascent iter/s, heavy-tailed blocks with mixed projections"
+        workload = ("matching LP: I=%d sources, J=%d destinations, degree Pareto(1.2, scale 6.5) "
+                    "clipped to [1, 4096], Zipf(1.1) destinations, 70%% simplex / 30%% box blocks, "
+                    "gamma=1e-3, gap test every %d iterations" %
+                    (args.sources, args.dests, args.check_every))
     out = {
-        "metric": "dual-ascent iter/s at 100M nnz (matching LP, FP32-stored a and c)",
+        "metric": metric,
         "value": ips,
         "unit": "iter/s",
         "n_gpus": 1,
@@ -300,11 +324,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "matching LP: I=%d sources, J=%d destinations, degree "
-                               "1+Poisson(9), Zipf(1.1) destinations, simplex blocks, "
-                               "gamma=1e-3, gap test every %d iterations" %
-                               (args.sources, args.dests, args.check_every),
-                   "nnz": inst.n, "storage": args.storage, "seed": inst.seed},
+        "config": {"workload": workload, "nnz": inst.n, "storage": args.storage,
+                   "seed": inst.seed},
         "nnz_per_s": inst.n * ips,
         "stream_gbs": bytes_per * ips / 1e9,
         "grad_kernel_ms": r.grad_kernel_ms,
@@ -322,7 +343,7 @@ def main():
         lam_b = I.greedy_capacity(inst.dst, inst.a, inst.block_off, inst.m,
                                   [inst.seed, 1, 2])
         inst_b = I.Instance(inst.m, inst.n, inst.dst, inst.a, inst.c, lam_b, inst.block_off,
-                            inst.block_proj, None, "large-binding", inst.seed)
+                            inst.block_proj, inst.upper, args.config + "-binding", inst.seed)
         prob.close()
         with Problem(inst_b, storage=args.storage) as pb:
             _, rb, elb = timed(pb)

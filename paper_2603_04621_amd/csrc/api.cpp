@@ -436,15 +436,16 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     const int cus = device_cus(p->device);
     int nch = (int)std::min<int64_t>(cus, std::max<int64_t>(1, (n + 32767) / 32768));
     HostLayout L;
-    build_items(d, nch, opts.storage == DL_F64 ? kLaneMaxDegF64 : kLaneMaxDeg, L);
+    const size_t max_lds = device_max_lds(p->device);
+    int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
+    p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
+    const int lane_max = lane_cap(opts.storage == DL_F64, p->has_w != 0, p->K < m);
+    build_items(d, nch, lane_max, L);
     p->nchunks = nch;
     p->nitems = (int)L.items.size();
     p->n_lane = L.n_lane;
     p->n_wave = L.n_wave;
     p->n_wg = L.n_wg;
-    const size_t max_lds = device_max_lds(p->device);
-    int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
-    p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
     p->nblk2 = (p->J + 63) / 64;
 
     // stream arrays

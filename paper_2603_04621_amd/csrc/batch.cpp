@@ -63,24 +63,25 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
         a0[k] = agd_args(p, prm[k], 0, nullptr);
         a1[k] = agd_args(p, prm[k], 1, nullptr);
     }
-    // groups by kernel variant; within a group the largest problems go first
-    std::map<std::pair<int, int>, std::vector<int>> by;
-    for (int k = 0; k < n; ++k) by[{probs[k]->storage, probs[k]->has_w}].push_back(k);
+    // groups by kernel variant (storage, weights, rows beyond LDS: the layout
+    // of each problem matches its variant); the largest problems go first
+    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    for (int k = 0; k < n; ++k)
+        by[{probs[k]->storage, probs[k]->has_w, probs[k]->K < probs[k]->J ? 1 : 0}].push_back(k);
     std::vector<int2> ct, rb;
     for (auto& kv : by) {
         auto idx = kv.second;
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return probs[a]->n > probs[b]->n; });
         Group G;
-        G.storage = kv.first.first;
-        G.has_w = kv.first.second;
-        G.tail = 0;
+        G.storage = std::get<0>(kv.first);
+        G.has_w = std::get<1>(kv.first);
+        G.tail = std::get<2>(kv.first);
         G.lds = 0;
         G.c0 = (int)ct.size();
         // round-robin over problems so long chunks of big problems start early
         int maxc = 0;
         for (int k : idx) {
             maxc = std::max(maxc, probs[k]->nchunks);
-            G.tail |= probs[k]->K < probs[k]->J;
             G.lds = std::max({G.lds, grad_lds_bytes(probs[k]->K, false), grad_lds_bytes(probs[k]->K, true)});
         }
         for (int c = 0; c < maxc; ++c)

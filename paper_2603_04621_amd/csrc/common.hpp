@@ -37,6 +37,16 @@ constexpr int kLaneMaxDeg = 32;         // LANE items (registers: 32 edges per l
 constexpr int kLaneMaxDegF64 = 8;       // LANE items with FP64 storage
 constexpr int kWaveMaxDeg = 512;        // WAVE items (8 edges per lane)
 
+// Largest LANE degree of a problem: 8 with FP64 storage; 16 when per-edge
+// weights or rows beyond LDS add registers (the 24- and 32-edge lane groups
+// would spill there), else 32.  The host lays the stream out with it and the
+// kernel variant of the same (storage, weights, tail) compiles only these
+// lane classes.
+constexpr int lane_cap(bool f64, bool has_w, bool tail)
+{
+    return f64 ? kLaneMaxDegF64 : ((has_w || tail) ? 16 : kLaneMaxDeg);
+}
+
 enum ItemKind : uint8_t { ITEM_LANE = 0, ITEM_WAVE = 1, ITEM_WG = 2 };
 
 struct Item {                // 16 bytes

@@ -330,6 +330,35 @@ __device__ __forceinline__ void lane_t(const GradArgs& g, const Lds& s, const La
     }
 }
 
+// lam gathers of rows [0, P) (global or buffer loads on passes that read lam
+// from memory) and the t phase that consumes them, for the pipelined runs
+template <typename VT, bool CHECK, bool TAIL, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_gather(const GradArgs& g, const Lds& s, const LaneRaw<VT, BOX, HASW, P>& r,
+                                            double (&lam)[P])
+{
+#pragma unroll
+    for (int k = 0; k < P; ++k) lam[k] = get_lam<CHECK, TAIL>(s, g, r.j[k]);
+}
+
+template <typename VT, bool CHECK, bool TAIL, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_t_gathered(const LaneGeo& q, const LaneRaw<VT, BOX, HASW, P>& r,
+                                                const double (&lam)[P], LaneVals<VT, CHECK, BOX, HASW, P>& v)
+{
+    using R = typename Val<VT>::reg;
+    const bool act = (int)(threadIdx.x & 63) < q.nb;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        v.a[k] = Val<VT>::cvt(r.a[k]);
+        const R c = Val<VT>::cvt(r.c[k]);
+        v.j[k] = r.j[k];
+        if (BOX) v.u[k] = r.u[k];
+        if (HASW) v.w[k] = r.w[k];
+        const double tk = -((double)c + (double)v.a[k] * lam[k]);
+        v.t[k] = (k < q.d && act) ? tk : -INFINITY;
+        if (CHECK) v.c[k] = c;
+    }
+}
+
 // projection phase: simplex threshold in registers, then x, the objective
 // and the per-destination sums
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
@@ -406,7 +435,9 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
                 int n2 = 0;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    const double w = (double)v.w[HASW ? k : 0] * inv_g;
+                    // recomputed each round (opaque): hoisting P FP64 weights
+                    // out of the loop would cost 2P registers
+                    const double w = (double)opq(v.w[HASW ? k : 0]) * inv_g;
                     const bool in = t[k] > tn;
                     sw2 += in ? w : 0.0;
                     swt2 += in ? w * t[k] : 0.0;
@@ -477,16 +508,32 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
     const LaneGeo q = lane_geo(it);
     LaneRaw<VT, BOX, HASW, P> r;
     LaneVals<VT, CHECK, BOX, HASW, P> v;
-    constexpr int T = P < 16 ? P : 16;
+    // (rows beyond LDS gather lam with a second load per row: smaller tiles)
+    constexpr int T0 = TAIL ? 8 : 16;
+    constexpr int T = P < T0 ? P : T0;
     lane_load<0, T>(g, q, r);
     __builtin_amdgcn_sched_barrier(0);
     lane_t<0, T, VT, CHECK, TAIL>(g, s, q, r, v);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (P > T) {
-        lane_load<T, P>(g, q, r);
+        constexpr int T2 = P < 2 * T ? P : 2 * T;
+        lane_load<T, T2>(g, q, r);
         __builtin_amdgcn_sched_barrier(0);
-        lane_t<T, P, VT, CHECK, TAIL>(g, s, q, r, v);
+        lane_t<T, T2, VT, CHECK, TAIL>(g, s, q, r, v);
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (P > T2) {
+            constexpr int T3 = P < 3 * T ? P : 3 * T;
+            lane_load<T2, T3>(g, q, r);
+            __builtin_amdgcn_sched_barrier(0);
+            lane_t<T2, T3, VT, CHECK, TAIL>(g, s, q, r, v);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (P > T3) {
+                lane_load<T3, P>(g, q, r);
+                __builtin_amdgcn_sched_barrier(0);
+                lane_t<T3, P, VT, CHECK, TAIL>(g, s, q, r, v);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
     }
     lane_project<VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
 }
@@ -516,9 +563,9 @@ __device__ __forceinline__ Item item_at(const Item& mine, int r)
 // a run of lane groups of one size class P <= 16 starting at batch entry r:
 // the next group's loads are in flight while the current group projects.
 // Ordinary passes (lam from LDS) issue them before the t phase; passes that
-// gather lam from global memory issue them after it, so that waiting for the
-// lam loads never waits for the prefetch as well.  Returns the first entry
-// not processed.
+// gather lam from memory issue the gathers first, then the prefetch, so that
+// waiting for the gathers (older in the in-order memory counter) never waits
+// for the prefetch as well.  Returns the first entry not processed.
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
 __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int r, const int rn, const Lds& s,
                                         double gamma, Obj& ob)
@@ -549,9 +596,12 @@ __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int
             __builtin_amdgcn_sched_barrier(0);
             lane_t<0, P, VT, CHECK, TAIL>(g, s, q, cur, v);
         } else {
-            lane_t<0, P, VT, CHECK, TAIL>(g, s, q, cur, v);
+            double lam[P];
+            lane_gather<VT, CHECK, TAIL>(g, s, cur, lam);
             __builtin_amdgcn_sched_barrier(0);
             lane_load<0, P>(g, qn, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+            lane_t_gathered<VT, CHECK, TAIL>(q, cur, lam, v);
         }
         __builtin_amdgcn_sched_barrier(0);
         lane_project<VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
@@ -843,14 +893,33 @@ template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
 __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine, const int r, const int rn,
                                              const Item& it, const Lds& s, double gamma, Obj& ob)
 {
-    // FP64 storage keeps blocks of at most 8 edges in lanes (register budget)
+    // FP64 storage keeps blocks of at most 8 edges in lanes (register budget);
+    // per-edge weights (and rows beyond LDS) need more registers, so their
+    // pipelined runs stop at smaller classes and their lane blocks at 16
+    // edges (the layout guarantees d <= CAP)
+    constexpr bool W8 = sizeof(VT) == 8;
+    constexpr int PIPE = W8 ? 8 : (HASW ? 8 : (TAIL ? 12 : 16));
+    constexpr int CAP = lane_cap(W8, HASW, TAIL);
     switch (lane_class<VT>(it.d)) {
     case 4: return lane_run<VT, CHECK, HASW, TAIL, BOX, 4>(g, mine, r, rn, s, gamma, ob);
-    case 8: return lane_run<VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
-    case 12: return lane_run<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
-    case 16: return lane_run<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
-    case 24: lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 24>(g, it, s, gamma, ob); return r + 1;
-    default: lane_group<VT, CHECK, HASW, TAIL, BOX, sizeof(VT) == 8 ? 8 : 32>(g, it, s, gamma, ob); return r + 1;
+    case 8:
+        if constexpr (PIPE >= 8) return lane_run<VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
+        lane_group<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
+        return r + 1;
+    case 12:
+        if constexpr (PIPE >= 12) return lane_run<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
+        lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, it, s, gamma, ob);
+        return r + 1;
+    case 16:
+        if constexpr (PIPE >= 16) return lane_run<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
+        lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, it, s, gamma, ob);
+        return r + 1;
+    case 24:
+        if constexpr (CAP > 16) lane_group<VT, CHECK, HASW, TAIL, BOX, 24>(g, it, s, gamma, ob);
+        return r + 1;
+    default:
+        if constexpr (CAP > 24) lane_group<VT, CHECK, HASW, TAIL, BOX, 32>(g, it, s, gamma, ob);
+        return r + 1;
     }
 }
 
