@@ -244,7 +244,9 @@ dl_status dl_server_destroy(dl_server* s);
 /* Layout and size figures of a created problem. */
 typedef struct {
     int64_t m, n, num_blocks;
-    int64_t lane_groups, wave_blocks, wg_blocks;   /* work items by kind            */
+    int64_t lane_groups, seg_groups, wg_blocks;   /* work items: one-lane-per-block
+                                                   groups, multi-lane groups,
+                                                   one-workgroup blocks          */
     int64_t chunks, lds_rows;                      /* workgroups, rows kept in LDS  */
     int64_t stream_bytes;      /* per-nonzero bytes streamed by one gradient pass */
     int64_t device_bytes;      /* device memory held by the problem              */

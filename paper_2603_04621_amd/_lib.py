@@ -63,7 +63,7 @@ class SolveResult(ctypes.Structure):
 
 
 class ProblemInfo(ctypes.Structure):
-    _fields_ = [(k, c_i64) for k in ("m", "n", "num_blocks", "lane_groups", "wave_blocks",
+    _fields_ = [(k, c_i64) for k in ("m", "n", "num_blocks", "lane_groups", "seg_groups",
                                      "wg_blocks", "chunks", "lds_rows", "stream_bytes",
                                      "device_bytes")] + [("storage", c_i32), ("has_box", c_i32)]
 

@@ -217,80 +217,88 @@ struct HostLayout {
     std::vector<Item> items;
     std::vector<Chunk> chunks;
     std::vector<int64_t> src;      // stream position -> original column
-    int64_t nA = 0, nB = 0;        // wave items / workgroup items
-    int64_t n_lane = 0, n_wave = 0, n_wg = 0;
+    int64_t n_lane = 0, n_seg = 0, n_wg = 0;   // one-lane groups, multi-lane groups, WG blocks
 };
 
-// Groups blocks by (kind, projection, degree), deals the work items of each
-// kind round-robin to the chunks (in degree order, so every chunk gets the
-// same mix of sizes and the same share of nonzeros: a chunk's time follows
-// its number of items as much as its nonzeros) and lays the stream out chunk
-// by chunk, so each workgroup reads one contiguous region per kind.
-static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, HostLayout& L)
+// Lanes per block (log2) of a block of d edges: 0 up to cap, else the
+// smallest S in {4, 16, 64} with ceil(d / S) <= rmax rows per lane; -1 for
+// WG blocks.
+static int block_lg(int64_t d, int cap, int rmax)
+{
+    if (d <= cap) return 0;
+    for (int lg = 2; lg <= 6; lg += 2)
+        if ((d + (1 << lg) - 1) >> lg <= rmax) return lg;
+    return -1;
+}
+
+// Groups blocks by (lanes per block, projection, degree), deals the work
+// items of each kind round-robin to the chunks (in that order, so every
+// chunk gets the same mix of sizes and the same share of nonzeros: a chunk's
+// time follows its number of items as much as its nonzeros) and lays the
+// stream out chunk by chunk, so each workgroup reads one contiguous region
+// per kind.
+static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, HostLayout& L)
 {
     const int64_t I = d->num_blocks;
-    // bucket keys: lane kinds by (proj, d), then wave kinds by (proj, d), then wg by proj
-    std::vector<std::vector<int64_t>> lane(2 * (kLaneMaxDeg + 1));
-    std::vector<std::pair<int64_t, int64_t>> wave, wgb;   // (key, block)
+    const int64_t dmax_lane = std::max<int64_t>(cap, 64 * (int64_t)rmax);
+    // buckets: [lg / 2][proj][degree] for LANE items, then WG blocks by proj
+    std::vector<std::vector<int64_t>> lane((size_t)4 * 2 * (dmax_lane + 1));
+    auto bucket = [&](int lg, int pr, int64_t deg) -> std::vector<int64_t>& {
+        return lane[((size_t)(lg / 2) * 2 + pr) * (dmax_lane + 1) + deg];
+    };
+    std::vector<std::pair<int64_t, int64_t>> wgb;   // (proj, block)
     for (int64_t i = 0; i < I; ++i) {
         const int64_t deg = d->block_off[i + 1] - d->block_off[i];
         const int pr = d->block_proj[i];
         if (deg == 0) continue;
-        if (deg <= lane_max) lane[(size_t)pr * (kLaneMaxDeg + 1) + deg].push_back(i);
-        else if (deg <= kWaveMaxDeg) wave.push_back({(int64_t)pr * (kWaveMaxDeg + 1) + deg, i});
+        const int lg = block_lg(deg, cap, rmax);
+        if (lg >= 0) bucket(lg, pr, deg).push_back(i);
         else wgb.push_back({(int64_t)pr, i});
     }
-    std::stable_sort(wave.begin(), wave.end(), [](auto& a, auto& b) { return a.first < b.first; });
     std::stable_sort(wgb.begin(), wgb.end(), [](auto& a, auto& b) { return a.first < b.first; });
 
-    // items of each kind in (proj, degree) order; gb holds their blocks
+    // items of each kind in order; gb holds their blocks
     struct Proto {
         Item it;
         int64_t g0;   // first block in gb
     };
-    std::vector<Proto> kinds[3];
+    std::vector<Proto> kinds[2];
     std::vector<int64_t> gb;
-    for (int pr = 0; pr < 2; ++pr)
-        for (int deg = 1; deg <= kLaneMaxDeg; ++deg) {
-            const auto& v = lane[(size_t)pr * (kLaneMaxDeg + 1) + deg];
-            for (size_t s0 = 0; s0 < v.size(); s0 += 64) {
-                const int nb = (int)std::min<size_t>(64, v.size() - s0);
-                Proto q;
-                q.it = Item{0, deg, (uint16_t)nb, (uint8_t)ITEM_LANE, (uint8_t)pr};
-                q.g0 = (int64_t)gb.size();
-                for (int l = 0; l < nb; ++l) gb.push_back(v[s0 + l]);
-                kinds[0].push_back(q);
+    for (int lg = 0; lg <= 6; lg += 2)
+        for (int pr = 0; pr < 2; ++pr)
+            for (int64_t deg = 1; deg <= dmax_lane; ++deg) {
+                const auto& v = bucket(lg, pr, deg);
+                const size_t per = (size_t)64 >> lg;
+                for (size_t s0 = 0; s0 < v.size(); s0 += per) {
+                    const int nb = (int)std::min<size_t>(per, v.size() - s0);
+                    Proto q;
+                    q.it = Item{0, (int32_t)deg, (uint8_t)nb, (uint8_t)lg, (uint8_t)ITEM_LANE, (uint8_t)pr};
+                    q.g0 = (int64_t)gb.size();
+                    for (int l = 0; l < nb; ++l) gb.push_back(v[s0 + l]);
+                    kinds[0].push_back(q);
+                    if (lg == 0) ++L.n_lane;
+                    else ++L.n_seg;
+                }
             }
-        }
-    for (auto& kv : wave) {
+    for (auto& kv : wgb) {
         const int64_t i = kv.second;
         Proto q;
-        q.it = Item{0, (int32_t)(d->block_off[i + 1] - d->block_off[i]), 1, (uint8_t)ITEM_WAVE, d->block_proj[i]};
+        q.it = Item{0, (int32_t)(d->block_off[i + 1] - d->block_off[i]), 1, 0, (uint8_t)ITEM_WG, d->block_proj[i]};
         q.g0 = (int64_t)gb.size();
         gb.push_back(i);
         kinds[1].push_back(q);
     }
-    for (auto& kv : wgb) {
-        const int64_t i = kv.second;
-        Proto q;
-        q.it = Item{0, (int32_t)(d->block_off[i + 1] - d->block_off[i]), 1, (uint8_t)ITEM_WG, d->block_proj[i]};
-        q.g0 = (int64_t)gb.size();
-        gb.push_back(i);
-        kinds[2].push_back(q);
-    }
-    L.n_lane = (int64_t)kinds[0].size();
-    L.n_wave = (int64_t)kinds[1].size();
-    L.n_wg = (int64_t)kinds[2].size();
+    L.n_wg = (int64_t)kinds[1].size();
 
     // deal: chunk c takes items c, c + nchunks, ... of each kind; stream
     // positions follow the final item order
-    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0, 0, 0});
+    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0});
     std::vector<int64_t> g0s;
     int64_t pos = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 2; ++k) {
         const auto& v = kinds[k];
         for (int c = 0; c < nchunks; ++c) {
-            int32_t* r = k == 0 ? &L.chunks[c].a0 : (k == 1 ? &L.chunks[c].w0 : &L.chunks[c].b0);
+            int32_t* r = k == 0 ? &L.chunks[c].a0 : &L.chunks[c].b0;
             r[0] = (int32_t)L.items.size();
             for (size_t q = (size_t)c; q < v.size(); q += (size_t)nchunks) {
                 Item it = v[q].it;
@@ -301,11 +309,11 @@ static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, Hos
             }
             r[1] = (int32_t)L.items.size();
         }
-        if (k == 1) L.nA = (int64_t)L.items.size();
     }
-    L.nB = (int64_t)L.items.size() - L.nA;
 
-    // stream position -> original column
+    // stream position -> original column: edge e = k S + s of block b of a
+    // LANE group sits at base + k nb S + b S + s for k < R - 1, and the last
+    // row is compacted: base + (R - 1) nb S + b rem + s
     L.src.assign((size_t)pos, 0);
     const int64_t nit = (int64_t)L.items.size();
     parallel_for(nit, 4096, [&](int64_t lo, int64_t hi) {
@@ -313,9 +321,15 @@ static void build_items(const dl_problem_desc* d, int nchunks, int lane_max, Hos
             const Item& it = L.items[q];
             const int64_t g0 = g0s[q];
             if (it.kind == ITEM_LANE) {
-                for (int l = 0; l < it.nb; ++l) {
+                const int64_t S = (int64_t)1 << it.lg, nb = it.nb, deg = it.d;
+                const int64_t R = (deg + S - 1) / S, rem = deg - (R - 1) * S, W = nb * S;
+                for (int64_t l = 0; l < nb; ++l) {
                     const int64_t c0 = d->block_off[gb[g0 + l]];
-                    for (int k = 0; k < it.d; ++k) L.src[it.base + (int64_t)k * it.nb + l] = c0 + k;
+                    for (int64_t e = 0; e < deg; ++e) {
+                        const int64_t k = e / S, s = e % S;
+                        const int64_t off = k < R - 1 ? k * W + l * S + s : (R - 1) * W + l * rem + s;
+                        L.src[it.base + off] = c0 + e;
+                    }
                 }
             } else {
                 const int64_t c0 = d->block_off[gb[g0]];
@@ -439,12 +453,12 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     const size_t max_lds = device_max_lds(p->device);
     int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
     p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
-    const int lane_max = lane_cap(opts.storage == DL_F64, p->has_w != 0, p->K < m);
-    build_items(d, nch, lane_max, L);
+    const bool f64 = opts.storage == DL_F64, tail = p->K < m;
+    build_items(d, nch, lane_cap(f64, p->has_w != 0, tail), seg_rmax(f64, p->has_w != 0, tail), L);
     p->nchunks = nch;
     p->nitems = (int)L.items.size();
     p->n_lane = L.n_lane;
-    p->n_wave = L.n_wave;
+    p->n_seg = L.n_seg;
     p->n_wg = L.n_wg;
     p->nblk2 = (p->J + 63) / 64;
 
@@ -559,7 +573,7 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* i
     info->n = p->n;
     info->num_blocks = p->nblocks;
     info->lane_groups = p->n_lane;
-    info->wave_blocks = p->n_wave;
+    info->seg_groups = p->n_seg;
     info->wg_blocks = p->n_wg;
     info->chunks = p->nchunks;
     info->lds_rows = p->K;

@@ -8,20 +8,21 @@
 //   iv_e = 1/v_e^2 (primal scale, f32) and perm_e (original column, int64,
 //   only read when x is requested).
 //
-//   Work items.  Blocks are grouped by projection type and degree d:
-//     LANE  d <= 32 (8 for FP64 storage): groups of up to 64 blocks of one
-//           exact degree; lane l of a
-//           wave owns block l of the group, whose k-th edge is stored at
-//           base + k*nb + l, so every load of the wave is one contiguous
-//           nb-element run (coalesced) and the whole projection runs in the
-//           lane's registers.
-//     WAVE  up to d <= 512: one wave per block, edge k at base + k.
-//     WG    d > 512: one workgroup per block, edge k at base + k.
+//   Work items.  Blocks are grouped by projection type and degree d into
+//   LANE items: groups of nb blocks of one exact degree, each block on
+//   S = 2^lg consecutive lanes of a wave (S = 1 up to d <= lane_cap, else
+//   the smallest S in {4, 16, 64} with ceil(d/S) <= seg_rmax rows per lane),
+//   edge k S + s of block b at base + k nb S + b S + s for the full rows and
+//   the last row compacted (see grad_impl.hpp), so every load of a row is
+//   one contiguous run and the projection runs in registers with reductions
+//   over the block's lanes.  Blocks longer than 64 seg_rmax edges are WG
+//   items: one workgroup per block, edge k at base + k.
 //
 //   Chunks.  The workgroups of the fused gradient kernel each take one
-//   chunk: an equal share (by nonzeros) of the LANE items, of the WAVE items
-//   (both spread over the chunk's waves) and of the WG items.  Each chunk owns one row of the
-//   per-destination partial-sum buffer, so results do not depend on timing.
+//   chunk: the LANE items dealt round-robin in (S, projection, degree) order,
+//   and likewise the WG items, so every chunk gets the same mix of sizes.
+//   Each chunk owns one row of the per-destination partial-sum buffer, so
+//   results do not depend on timing.
 //
 //   Destinations.  Relabelled by descending degree; the first K (lds_rows)
 //   live in LDS during the gradient pass (lam in FP64 and f32 partial sums),
@@ -33,33 +34,39 @@ namespace dl {
 
 constexpr int kWG = 512;                // threads of a gradient workgroup
 constexpr int kWaves = kWG / 64;
-constexpr int kLaneMaxDeg = 32;         // LANE items (registers: 32 edges per lane)
-constexpr int kLaneMaxDegF64 = 8;       // LANE items with FP64 storage
-constexpr int kWaveMaxDeg = 512;        // WAVE items (8 edges per lane)
+constexpr int kLaneMaxDeg = 32;         // one-lane blocks (registers: 32 edges per lane)
+constexpr int kLaneMaxDegF64 = 8;       // one-lane blocks with FP64 storage
 
-// Largest LANE degree of a problem: 8 with FP64 storage; 16 when per-edge
-// weights or rows beyond LDS add registers (the 24- and 32-edge lane groups
-// would spill there), else 32.  The host lays the stream out with it and the
-// kernel variant of the same (storage, weights, tail) compiles only these
-// lane classes.
+// Largest degree of a one-lane block (S = 1): 8 with FP64 storage; 16 when
+// per-edge weights or rows beyond LDS add registers (the 24- and 32-edge
+// groups would spill there), else 32.  The host lays the stream out with it
+// and the kernel variant of the same (storage, weights, tail) compiles only
+// these classes.
 constexpr int lane_cap(bool f64, bool has_w, bool tail)
 {
     return f64 ? kLaneMaxDegF64 : ((has_w || tail) ? 16 : kLaneMaxDeg);
 }
+// Largest rows per lane of a multi-lane block (S > 1); blocks longer than
+// 64 * seg_rmax edges are WG items.
+constexpr int seg_rmax(bool f64, bool has_w, bool tail)
+{
+    return f64 ? 8 : (has_w ? 8 : (tail ? 12 : 16));
+}
 
-enum ItemKind : uint8_t { ITEM_LANE = 0, ITEM_WAVE = 1, ITEM_WG = 2 };
+enum ItemKind : uint8_t { ITEM_LANE = 0, ITEM_WG = 2 };
 
 struct Item {                // 16 bytes
     int64_t base;            // first stream position
     int32_t d;               // degree (edges per block)
-    uint16_t nb;             // blocks in the group (LANE), 1 otherwise
+    uint8_t nb;              // blocks in the group (LANE), 1 otherwise
+    uint8_t lg;              // log2 of lanes per block (LANE)
     uint8_t kind;            // ItemKind
     uint8_t proj;            // dl_proj
 };
 static_assert(sizeof(Item) == 16, "Item layout");
 
-struct Chunk {               // lane groups [a0, a1), wave blocks [w0, w1), workgroup blocks [b0, b1)
-    int32_t a0, a1, w0, w1, b0, b1;
+struct Chunk {               // lane items [a0, a1), workgroup blocks [b0, b1)
+    int32_t a0, a1, b0, b1;
 };
 
 // Scalars of the iteration that live on the device (one per solve slot).

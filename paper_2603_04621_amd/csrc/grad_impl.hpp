@@ -242,25 +242,103 @@ struct Obj {
 };
 
 // ---------------------------------------------------------------------------
-// LANE items: one lane per block, the block's d <= P values in registers.
-// A group is handled in three steps: the loads of its stored values, the
-// t phase (gather lam, t in FP64) and the projection phase (threshold, x,
-// objective, per-destination sums).  Runs of groups of one size class are
+// LANE items (block-to-wavefront binning).  A group holds nb blocks of one
+// degree d.  Each block owns S = 2^lg consecutive lanes of a wave (S = 1: one
+// lane per block, up to 64 blocks; S = 64: one block per wave) and each lane
+// keeps up to P of its block's edges in registers.  Edge e = k S + s of block
+// b (lane b S + s) is stored at base + k nb S + b S + s for the R - 1 full
+// rows; the last row (rem = d - (R - 1) S edges per block) is stored
+// compacted at base + (R - 1) nb S + b rem + s.  A group is exactly nb d
+// positions, every row of loads is one contiguous run, and S = 1 is the
+// plain lane-interleaved layout (edge k of block b at base + k nb + b).
+//
+// A group is handled in three steps: the loads of its stored values, the t
+// phase (gather lam, t in FP64) and the projection phase (threshold, x,
+// objective, per-destination sums).  With S > 1 the threshold sums are
+// reduced over the block's S lanes with butterfly shuffles (every lane of
+// the segment gets the same bits).  Runs of groups of one class are
 // software-pipelined: the loads of the next group are issued before the
 // projection phase of the current one, so a wave keeps memory busy while it
 // computes.
 // ---------------------------------------------------------------------------
-struct LaneGeo {
+struct SegGeo {
     int64_t ib;   // stream offset of the group
-    int d, nb;    // rows (edges per block), blocks (lanes in use)
+    int d, nb;    // degree, blocks in the group
+    int R, rem;   // rows per lane, edges of the last row per block
 };
-__device__ __forceinline__ LaneGeo lane_geo(const Item& it)
+template <int S>
+__device__ __forceinline__ SegGeo seg_geo(const Item& it)
 {
-    LaneGeo q;
+    SegGeo q;
     q.ib = uni64(it.base);
     q.d = uni(it.d);
     q.nb = uni(it.nb);
+    if (S == 1) {
+        q.R = q.d;
+        q.rem = 1;
+    } else {
+        q.R = (q.d + S - 1) / S;
+        q.rem = q.d - (q.R - 1) * S;
+    }
     return q;
+}
+template <int S>
+__device__ __forceinline__ int seg_b()
+{
+    return (int)(threadIdx.x & 63) / S;
+}
+template <int S>
+__device__ __forceinline__ int seg_s()
+{
+    return (int)(threadIdx.x & 63) & (S - 1);
+}
+
+// offset from the group base of this lane's row k; rows beyond the block
+// re-read its last edge and idle lanes read the last block's, so every load
+// is unconditional and in bounds (32-bit offsets from a wave-uniform base)
+template <int S>
+__device__ __forceinline__ uint32_t seg_off(const SegGeo& q, int k)
+{
+    const int b = seg_b<S>();
+    const int bc = b < q.nb ? b : q.nb - 1;
+    const int kk = k < q.R ? k : q.R - 1;
+    if (S == 1) return (uint32_t)(kk * q.nb + bc);
+    const int s = seg_s<S>();
+    const int W = q.nb * S;
+    const int last = (q.R - 1) * W + bc * q.rem + (s < q.rem ? s : q.rem - 1);
+    return (uint32_t)(kk < q.R - 1 ? kk * W + bc * S + s : last);
+}
+// whether row k of this lane is an edge of its block
+template <int S>
+__device__ __forceinline__ bool seg_valid(const SegGeo& q, int k)
+{
+    const int b = seg_b<S>();
+    if (S == 1) return b < q.nb && k < q.d;
+    const int s = seg_s<S>();
+    return b < q.nb && (k < q.R - 1 || (k == q.R - 1 && s < q.rem));
+}
+
+// butterfly reductions over the S lanes of a segment
+template <int S>
+__device__ __forceinline__ double seg_sum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int S>
+__device__ __forceinline__ double seg_max(double v)
+{
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <int S>
+__device__ __forceinline__ int seg_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // stored values of rows k < P, as loaded
@@ -284,21 +362,16 @@ struct LaneVals {
     float w[HASW ? P : 1];
 };
 
-// loads of rows [K0, K1) (rows beyond d re-read row d-1 and idle lanes read
-// the last block, so every load is unconditional and in bounds; offsets are
-// 32-bit from a wave-uniform base)
-template <int K0, int K1, typename VT, bool BOX, bool HASW, int P>
-__device__ __forceinline__ void lane_load(const GradArgs& g, const LaneGeo& q, LaneRaw<VT, BOX, HASW, P>& r)
+// loads of rows [K0, K1)
+template <int K0, int K1, int S, typename VT, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_load(const GradArgs& g, const SegGeo& q, LaneRaw<VT, BOX, HASW, P>& r)
 {
-    const int lane = threadIdx.x & 63;
-    const int lc = lane < q.nb ? lane : q.nb - 1;
     const VT* __restrict__ A = (const VT*)g.A + q.ib;
     const VT* __restrict__ C = (const VT*)g.C + q.ib;
     const int32_t* __restrict__ Dst = g.dst + q.ib;
 #pragma unroll
     for (int k = K0; k < K1; ++k) {
-        const int kk = k < q.d ? k : q.d - 1;
-        const uint32_t off = (uint32_t)(lc + kk * q.nb);
+        const uint32_t off = seg_off<S>(q, k);
         r.a[k] = ldo(A, off);
         r.c[k] = ldo(C, off);
         r.j[k] = ldo(Dst, off);
@@ -307,27 +380,31 @@ __device__ __forceinline__ void lane_load(const GradArgs& g, const LaneGeo& q, L
     }
 }
 
-// t phase of rows [K0, K1): t_e = -(c_e + a_e lam_j(e)) in FP64; rows beyond
-// d and idle lanes get t = -inf (never active)
-template <int K0, int K1, typename VT, bool CHECK, bool TAIL, bool BOX, bool HASW, int P>
-__device__ __forceinline__ void lane_t(const GradArgs& g, const Lds& s, const LaneGeo& q,
+// t of row k from its stored values and lam: t_e = -(c_e + a_e lam_j(e)) in
+// FP64; rows that are no edge of the lane's block get t = -inf (never active)
+template <int S, typename VT, bool CHECK, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_t_row(const SegGeo& q, const LaneRaw<VT, BOX, HASW, P>& r, const int k,
+                                           const double lam, LaneVals<VT, CHECK, BOX, HASW, P>& v)
+{
+    using R = typename Val<VT>::reg;
+    v.a[k] = Val<VT>::cvt(r.a[k]);
+    const R c = Val<VT>::cvt(r.c[k]);
+    v.j[k] = r.j[k];
+    if (BOX) v.u[k] = r.u[k];
+    if (HASW) v.w[k] = r.w[k];
+    const double tk = -((double)c + (double)v.a[k] * lam);
+    v.t[k] = seg_valid<S>(q, k) ? tk : -INFINITY;
+    if (CHECK) v.c[k] = c;
+}
+
+// t phase of rows [K0, K1), lam gathered here
+template <int K0, int K1, int S, typename VT, bool CHECK, bool TAIL, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_t(const GradArgs& g, const Lds& s, const SegGeo& q,
                                        const LaneRaw<VT, BOX, HASW, P>& r,
                                        LaneVals<VT, CHECK, BOX, HASW, P>& v)
 {
-    using R = typename Val<VT>::reg;
-    const bool act = (int)(threadIdx.x & 63) < q.nb;
 #pragma unroll
-    for (int k = K0; k < K1; ++k) {
-        v.a[k] = Val<VT>::cvt(r.a[k]);
-        const R c = Val<VT>::cvt(r.c[k]);
-        v.j[k] = r.j[k];
-        if (BOX) v.u[k] = r.u[k];
-        if (HASW) v.w[k] = r.w[k];
-        const double lam = get_lam<CHECK, TAIL>(s, g, v.j[k]);
-        const double tk = -((double)c + (double)v.a[k] * lam);
-        v.t[k] = (k < q.d && act) ? tk : -INFINITY;
-        if (CHECK) v.c[k] = c;
-    }
+    for (int k = K0; k < K1; ++k) lane_t_row<S>(q, r, k, get_lam<CHECK, TAIL>(s, g, r.j[k]), v);
 }
 
 // lam gathers of rows [0, P) (global or buffer loads on passes that read lam
@@ -339,37 +416,146 @@ __device__ __forceinline__ void lane_gather(const GradArgs& g, const Lds& s, con
 #pragma unroll
     for (int k = 0; k < P; ++k) lam[k] = get_lam<CHECK, TAIL>(s, g, r.j[k]);
 }
-
-template <typename VT, bool CHECK, bool TAIL, bool BOX, bool HASW, int P>
-__device__ __forceinline__ void lane_t_gathered(const LaneGeo& q, const LaneRaw<VT, BOX, HASW, P>& r,
+template <int S, typename VT, bool CHECK, bool BOX, bool HASW, int P>
+__device__ __forceinline__ void lane_t_gathered(const SegGeo& q, const LaneRaw<VT, BOX, HASW, P>& r,
                                                 const double (&lam)[P], LaneVals<VT, CHECK, BOX, HASW, P>& v)
 {
-    using R = typename Val<VT>::reg;
-    const bool act = (int)(threadIdx.x & 63) < q.nb;
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        v.a[k] = Val<VT>::cvt(r.a[k]);
-        const R c = Val<VT>::cvt(r.c[k]);
-        v.j[k] = r.j[k];
-        if (BOX) v.u[k] = r.u[k];
-        if (HASW) v.w[k] = r.w[k];
-        const double tk = -((double)c + (double)v.a[k] * lam[k]);
-        v.t[k] = (k < q.d && act) ? tk : -INFINITY;
-        if (CHECK) v.c[k] = c;
-    }
+    for (int k = 0; k < P; ++k) lane_t_row<S>(q, r, k, lam[k], v);
 }
 
-// projection phase: simplex threshold in registers, then x, the objective
-// and the per-destination sums
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
-__device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, const LaneGeo& q,
+// simplex threshold of blocks spread over S > 1 lanes: every lane holds
+// partial sums over its rows, reduced over the segment.  Segments iterate in
+// lock step (the loop runs while any segment of the wave is still moving,
+// finished ones hold their tau) so every shuffle sees the whole wave.
+template <int S, bool HASW, int P>
+__device__ __forceinline__ double seg_threshold(const double (&t)[P], const float (&wv)[HASW ? P : 1],
+                                                const double gamma, const double inv_g)
+{
+    double tau = 0.0;
+    if (!HASW) {
+        double sp = 0.0, mt = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            sp += t[k] > 0.0 ? t[k] : 0.0;
+            mt = t[k] > mt ? t[k] : mt;
+        }
+        sp = seg_sum<S>(sp);
+        mt = seg_max<S>(mt);
+        bool live = sp > gamma;
+        if (!__builtin_amdgcn_ballot_w64(live)) return 0.0;
+        double tv = live ? (mt - gamma > 0.0 ? mt - gamma : 0.0) : 0.0;
+        double st = 0.0;
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const bool in = t[k] > tv;
+            st += in ? t[k] : 0.0;
+            n += in ? 1 : 0;
+        }
+        st = seg_sum<S>(st);
+        n = seg_sum_i<S>(n);
+        const bool moved = live;
+#pragma unroll 1
+        for (int rep = 0; rep < 2 * P * S + 4; ++rep) {
+            if (!__builtin_amdgcn_ballot_w64(live)) break;
+            const double tn = live ? (st - gamma) / (double)n : tv;
+            double st2 = 0.0;
+            int n2 = 0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const bool in = t[k] > tn;
+                st2 += in ? t[k] : 0.0;
+                n2 += in ? 1 : 0;
+            }
+            st2 = seg_sum<S>(st2);
+            n2 = seg_sum_i<S>(n2);
+            if (live) {
+                tv = tn;
+                if (n2 >= n || n2 == 0) {
+                    live = false;
+                } else {
+                    st = st2;
+                    n = n2;
+                }
+            }
+        }
+        tau = moved ? tv : 0.0;
+    } else {
+        double s0 = 0.0, mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double w = (double)wv[HASW ? k : 0] * inv_g;
+            const double iw = gamma / (double)wv[HASW ? k : 0];
+            const double z = w * t[k];
+            s0 += z > 0.0 ? z : 0.0;
+            const double lo = t[k] - iw;
+            mx = lo > mx ? lo : mx;
+        }
+        s0 = seg_sum<S>(s0);
+        mx = seg_max<S>(mx);
+        bool live = s0 > 1.0;
+        if (!__builtin_amdgcn_ballot_w64(live)) return 0.0;
+        double tv = live ? (mx > 0.0 ? mx : 0.0) : 0.0;
+        double sw = 0.0, swt = 0.0;
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double w = (double)wv[HASW ? k : 0] * inv_g;
+            const bool in = t[k] > tv;
+            sw += in ? w : 0.0;
+            swt += in ? w * t[k] : 0.0;
+            n += in ? 1 : 0;
+        }
+        sw = seg_sum<S>(sw);
+        swt = seg_sum<S>(swt);
+        n = seg_sum_i<S>(n);
+        const bool moved = live;
+#pragma unroll 1
+        for (int rep = 0; rep < 2 * P * S + 4; ++rep) {
+            if (!__builtin_amdgcn_ballot_w64(live)) break;
+            const double tn = live ? (swt - 1.0) / sw : tv;
+            double sw2 = 0.0, swt2 = 0.0;
+            int n2 = 0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double w = (double)opq(wv[HASW ? k : 0]) * inv_g;
+                const bool in = t[k] > tn;
+                sw2 += in ? w : 0.0;
+                swt2 += in ? w * t[k] : 0.0;
+                n2 += in ? 1 : 0;
+            }
+            sw2 = seg_sum<S>(sw2);
+            swt2 = seg_sum<S>(swt2);
+            n2 = seg_sum_i<S>(n2);
+            if (live) {
+                tv = tn;
+                if (n2 >= n || n2 == 0) {
+                    live = false;
+                } else {
+                    sw = sw2;
+                    swt = swt2;
+                    n = n2;
+                }
+            }
+        }
+        tau = moved ? tv : 0.0;
+    }
+    return tau;
+}
+
+// projection phase: simplex threshold, then x, the objective and the
+// per-destination sums
+template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+__device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, const SegGeo& q,
                                              double gamma, Obj& ob, const LaneVals<VT, CHECK, BOX, HASW, P>& v)
 {
-    const int d = q.d;
     const double inv_g = 1.0 / gamma;
     const double* t = v.t;
     double tau = 0.0;
-    if (!BOX && !HASW) {
+    if (S > 1) {
+        if (!BOX) tau = seg_threshold<S, HASW, P>(v.t, v.w, gamma, inv_g);
+    } else if (!BOX && !HASW) {
         // uniform weight w = 1/gamma: sum max(0, w t) > 1  <=>  sum max(0, t) > gamma,
         // tau_0 = max(0, max t - gamma), tau <- (sum_S t - gamma) / |S|
         double sp = 0.0, mt = -INFINITY;
@@ -452,8 +638,8 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
         }
     }
 
-    // x, objective, per-destination sums of the LDS-resident rows (rows
-    // beyond d and idle lanes have t = -inf, hence x = 0, and are skipped)
+    // x, objective, per-destination sums of the LDS-resident rows (rows that
+    // are no edge have t = -inf, hence x = 0, and are skipped)
     bool tail = false;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -483,21 +669,18 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
         }
     }
     if (g.X) {
-        const int lane = threadIdx.x & 63;
-        if (lane < q.nb) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                if (k < d) {
-                    const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
-                    g.X[g.perm[q.ib + lane + (int64_t)k * q.nb]] = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
-                }
+        for (int k = 0; k < P; ++k) {
+            if (seg_valid<S>(q, k)) {
+                const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+                g.X[g.perm[q.ib + seg_off<S>(q, k)]] = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
             }
         }
     }
 }
 
-// one group of up to 32 rows, not pipelined: the loads go out in tiles of up
-// to 16 rows, each tile's loads all issued before their first use behind a
+// one group of up to 32 rows with S = 1, not pipelined: the loads go out in
+// tiles, each tile's loads all issued before their first use behind a
 // scheduling fence (left to itself the scheduler interleaves each row's loads
 // with its use, one memory round trip per row)
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
@@ -505,45 +688,51 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
                                            double gamma, Obj& ob)
 {
     static_assert(P <= 32, "lane blocks hold at most 32 edges");
-    const LaneGeo q = lane_geo(it);
+    const SegGeo q = seg_geo<1>(it);
     LaneRaw<VT, BOX, HASW, P> r;
     LaneVals<VT, CHECK, BOX, HASW, P> v;
     // (rows beyond LDS gather lam with a second load per row: smaller tiles)
     constexpr int T0 = TAIL ? 8 : 16;
     constexpr int T = P < T0 ? P : T0;
-    lane_load<0, T>(g, q, r);
+    lane_load<0, T, 1>(g, q, r);
     __builtin_amdgcn_sched_barrier(0);
-    lane_t<0, T, VT, CHECK, TAIL>(g, s, q, r, v);
+    lane_t<0, T, 1, VT, CHECK, TAIL>(g, s, q, r, v);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (P > T) {
         constexpr int T2 = P < 2 * T ? P : 2 * T;
-        lane_load<T, T2>(g, q, r);
+        lane_load<T, T2, 1>(g, q, r);
         __builtin_amdgcn_sched_barrier(0);
-        lane_t<T, T2, VT, CHECK, TAIL>(g, s, q, r, v);
+        lane_t<T, T2, 1, VT, CHECK, TAIL>(g, s, q, r, v);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (P > T2) {
             constexpr int T3 = P < 3 * T ? P : 3 * T;
-            lane_load<T2, T3>(g, q, r);
+            lane_load<T2, T3, 1>(g, q, r);
             __builtin_amdgcn_sched_barrier(0);
-            lane_t<T2, T3, VT, CHECK, TAIL>(g, s, q, r, v);
+            lane_t<T2, T3, 1, VT, CHECK, TAIL>(g, s, q, r, v);
             __builtin_amdgcn_sched_barrier(0);
             if constexpr (P > T3) {
-                lane_load<T3, P>(g, q, r);
+                lane_load<T3, P, 1>(g, q, r);
                 __builtin_amdgcn_sched_barrier(0);
-                lane_t<T3, P, VT, CHECK, TAIL>(g, s, q, r, v);
+                lane_t<T3, P, 1, VT, CHECK, TAIL>(g, s, q, r, v);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
-    lane_project<VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
+    lane_project<1, VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
 }
 
-// size class of a lane block of d edges (FP64 storage: at most 8)
-template <typename VT>
-__device__ __forceinline__ int lane_class(int d)
+// row class of a group: S = 1 by degree (FP64 storage: at most 8); S > 1 by
+// rows per lane, 8 or the variant's largest
+template <typename VT, bool HASW, bool TAIL>
+__device__ __forceinline__ int lane_class(int d, int lg)
 {
-    if (sizeof(VT) == 8) return d <= 4 ? 4 : 8;
-    return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : d <= 16 ? 16 : d <= 24 ? 24 : 32;
+    constexpr int RMAX = seg_rmax(sizeof(VT) == 8, HASW, TAIL);
+    if (lg == 0) {
+        if (sizeof(VT) == 8) return d <= 4 ? 4 : 8;
+        return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : d <= 16 ? 16 : d <= 24 ? 24 : 32;
+    }
+    const int R = (d + (1 << lg) - 1) >> lg;
+    return R <= 8 ? 8 : RMAX;
 }
 
 // item r of a batch of 64 descriptors held one per lane
@@ -553,244 +742,70 @@ __device__ __forceinline__ Item item_at(const Item& mine, int r)
     it.base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine.base >> 32), r) << 32) |
                         (uint32_t)__builtin_amdgcn_readlane((int)mine.base, r));
     it.d = __builtin_amdgcn_readlane(mine.d, r);
-    const int nbk = __builtin_amdgcn_readlane((int)mine.nb | ((int)mine.kind << 16) | ((int)mine.proj << 24), r);
-    it.nb = (uint16_t)(nbk & 0xFFFF);
-    it.kind = (uint8_t)((nbk >> 16) & 0xFF);
-    it.proj = (uint8_t)((nbk >> 24) & 0xFF);
+    const int pk = __builtin_amdgcn_readlane((int)mine.nb | ((int)mine.lg << 8) | ((int)mine.kind << 16) |
+                                                 ((int)mine.proj << 24),
+                                             r);
+    it.nb = (uint8_t)(pk & 0xFF);
+    it.lg = (uint8_t)((pk >> 8) & 0xFF);
+    it.kind = (uint8_t)((pk >> 16) & 0xFF);
+    it.proj = (uint8_t)((pk >> 24) & 0xFF);
     return it;
 }
 
-// a run of lane groups of one size class P <= 16 starting at batch entry r:
+// a run of groups of one class (S, P, projection) starting at batch entry r:
 // the next group's loads are in flight while the current group projects.
 // Ordinary passes (lam from LDS) issue them before the t phase; passes that
 // gather lam from memory issue the gathers first, then the prefetch, so that
 // waiting for the gathers (older in the in-order memory counter) never waits
 // for the prefetch as well.  Returns the first entry not processed.
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
 __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int r, const int rn, const Lds& s,
                                         double gamma, Obj& ob)
 {
     static_assert(P <= 16, "pipelined lane runs hold at most 16 rows per group");
+    constexpr int LG = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : S == 16 ? 4 : S == 32 ? 5 : 6;
+    static_assert((1 << LG) == S, "S is a power of two up to 64");
     constexpr bool EARLY = !CHECK && !TAIL;
-    LaneGeo q = lane_geo(item_at(mine, r));
+    SegGeo q = seg_geo<S>(item_at(mine, r));
     LaneRaw<VT, BOX, HASW, P> cur;
-    lane_load<0, P>(g, q, cur);
+    lane_load<0, P, S>(g, q, cur);
 #pragma unroll 1
     for (;;) {
         // the next group of this class, else the current one again (its
         // loads are in bounds and their values are never used)
         bool more = false;
-        LaneGeo qn = q;
+        SegGeo qn = q;
         if (r + 1 < rn) {
             const Item nx = item_at(mine, r + 1);
-            if ((nx.proj == 1) == BOX && nx.kind == 0 && lane_class<VT>(nx.d) == P) {
+            if ((nx.proj == 1) == BOX && nx.kind == ITEM_LANE && nx.lg == LG &&
+                lane_class<VT, HASW, TAIL>(nx.d, LG) == P) {
                 more = true;
-                qn = lane_geo(nx);
+                qn = seg_geo<S>(nx);
             }
         }
         LaneRaw<VT, BOX, HASW, P> nxt;
         LaneVals<VT, CHECK, BOX, HASW, P> v;
         __builtin_amdgcn_sched_barrier(0);
         if (EARLY) {
-            lane_load<0, P>(g, qn, nxt);
+            lane_load<0, P, S>(g, qn, nxt);
             __builtin_amdgcn_sched_barrier(0);
-            lane_t<0, P, VT, CHECK, TAIL>(g, s, q, cur, v);
+            lane_t<0, P, S, VT, CHECK, TAIL>(g, s, q, cur, v);
         } else {
             double lam[P];
             lane_gather<VT, CHECK, TAIL>(g, s, cur, lam);
             __builtin_amdgcn_sched_barrier(0);
-            lane_load<0, P>(g, qn, nxt);
+            lane_load<0, P, S>(g, qn, nxt);
             __builtin_amdgcn_sched_barrier(0);
-            lane_t_gathered<VT, CHECK, TAIL>(q, cur, lam, v);
+            lane_t_gathered<S>(q, cur, lam, v);
         }
         __builtin_amdgcn_sched_barrier(0);
-        lane_project<VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
+        lane_project<S, VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
         if (!more) break;
         cur = nxt;
         q = qn;
         ++r;
     }
     return r + 1;
-}
-
-// ---------------------------------------------------------------------------
-// WAVE items: one wave per block, edge e = lane + 64 k, k < P2
-// ---------------------------------------------------------------------------
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P2>
-__device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, const Lds& s,
-                                           double gamma, Obj& ob)
-{
-    using R = typename Val<VT>::reg;
-    const int lane = threadIdx.x & 63;
-    const int d = uni(it.d);
-    const int64_t ib = uni64(it.base);
-    const VT* __restrict__ A = (const VT*)g.A + ib;
-    const VT* __restrict__ C = (const VT*)g.C + ib;
-    const int32_t* __restrict__ Dst = g.dst + ib;
-    const double inv_g = 1.0 / gamma;
-    double t[P2];
-    R av[P2];
-    R cv[CHECK ? P2 : 1];
-    int jv[P2];
-    float uv[BOX ? P2 : 1];
-    float iv[HASW ? P2 : 1];
-    // all loads first, behind a scheduling fence (one round trip per block)
-    VT ar[P2], cr[P2];
-#pragma unroll
-    for (int k = 0; k < P2; ++k) {
-        const int e = lane + 64 * k;
-        const uint32_t ee = (uint32_t)(e < d ? e : d - 1);
-        ar[k] = ldo(A, ee);
-        cr[k] = ldo(C, ee);
-        jv[k] = ldo(Dst, ee);
-        if (BOX) uv[k] = ldo(g.U + ib, ee);
-        if (HASW) iv[k] = ldo(g.IV + ib, ee);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < P2; ++k) {
-        const int e = lane + 64 * k;
-        av[k] = Val<VT>::cvt(ar[k]);
-        const R c = Val<VT>::cvt(cr[k]);
-        const double lam = get_lam<CHECK, TAIL>(s, g, jv[k]);
-        const double tk = -((double)c + (double)av[k] * lam);
-        t[k] = e < d ? tk : -INFINITY;
-        if (CHECK) cv[k] = c;
-    }
-    double tau = 0.0;
-    if (!BOX && !HASW) {
-        double sp = 0.0, mt = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < P2; ++k) {
-            sp += t[k] > 0.0 ? t[k] : 0.0;
-            mt = fmax(mt, t[k]);
-        }
-        sp = wave_sum(sp);
-        mt = wave_max(mt);
-        if (sp > gamma) {
-            tau = mt - gamma > 0.0 ? mt - gamma : 0.0;
-            double st = 0.0;
-            int n = 0;
-#pragma unroll
-            for (int k = 0; k < P2; ++k) {
-                const bool in = t[k] > tau;
-                st += in ? t[k] : 0.0;
-                n += in ? 1 : 0;
-            }
-            st = wave_sum(st);
-            n = wave_sum_i(n);
-#pragma unroll 1
-            for (int rep = 0; rep < 2 * 64 * P2 + 4; ++rep) {
-                const double tn = (st - gamma) / (double)n;
-                double st2 = 0.0;
-                int n2 = 0;
-#pragma unroll
-                for (int k = 0; k < P2; ++k) {
-                    const bool in = t[k] > tn;
-                    st2 += in ? t[k] : 0.0;
-                    n2 += in ? 1 : 0;
-                }
-                st2 = wave_sum(st2);
-                n2 = wave_sum_i(n2);
-                tau = tn;
-                if (n2 >= n || n2 == 0) break;
-                st = st2;
-                n = n2;
-            }
-        }
-    } else if (!BOX) {
-        double s0 = 0.0, mx = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < P2; ++k) {
-            const double w = (double)iv[HASW ? k : 0] * inv_g;
-            const double iw = gamma / (double)iv[HASW ? k : 0];
-            const double z = w * t[k];
-            s0 += z > 0.0 ? z : 0.0;
-            mx = fmax(mx, t[k] - iw);
-        }
-        s0 = wave_sum(s0);
-        mx = wave_max(mx);
-        if (s0 > 1.0) {
-            tau = mx > 0.0 ? mx : 0.0;
-            double sw = 0.0, swt = 0.0;
-            int n = 0;
-#pragma unroll
-            for (int k = 0; k < P2; ++k) {
-                const double w = (double)iv[HASW ? k : 0] * inv_g;
-                const bool in = t[k] > tau;
-                sw += in ? w : 0.0;
-                swt += in ? w * t[k] : 0.0;
-                n += in ? 1 : 0;
-            }
-            sw = wave_sum(sw);
-            swt = wave_sum(swt);
-            n = wave_sum_i(n);
-#pragma unroll 1
-            for (int rep = 0; rep < 2 * 64 * P2 + 4; ++rep) {
-                const double tn = (swt - 1.0) / sw;
-                double sw2 = 0.0, swt2 = 0.0;
-                int n2 = 0;
-#pragma unroll
-                for (int k = 0; k < P2; ++k) {
-                    const double w = (double)iv[HASW ? k : 0] * inv_g;
-                    const bool in = t[k] > tn;
-                    sw2 += in ? w : 0.0;
-                    swt2 += in ? w * t[k] : 0.0;
-                    n2 += in ? 1 : 0;
-                }
-                sw2 = wave_sum(sw2);
-                swt2 = wave_sum(swt2);
-                n2 = wave_sum_i(n2);
-                tau = tn;
-                if (n2 >= n || n2 == 0) break;
-                sw = sw2;
-                swt = swt2;
-                n = n2;
-            }
-        }
-    }
-    bool tail = false;
-#pragma unroll
-    for (int k = 0; k < P2; ++k) {
-        const int e = lane + 64 * k;
-        if (e < d) {
-            const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-            const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
-            if (x != 0.0) {
-                const double q2 = HASW ? x * x / (double)iv[k] : x * x;
-                ob.ot += t[k] * x;
-                ob.oq += q2;
-                const double cx = CHECK ? (double)cv[k] * x : 0.0;
-                if (CHECK) ob.oc += cx;
-                if (!TAIL || jv[k] < g.K) accum_lds<CHECK>(s, jv[k], (double)opq(av[k]) * x, cx, q2);
-                else tail = true;
-            }
-        }
-    }
-    if (TAIL && __builtin_amdgcn_ballot_w64(tail)) {
-#pragma unroll
-        for (int k = 0; k < P2; ++k) {
-            const int e = lane + 64 * k;
-            if (e < d) {
-                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-                const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
-                if (x != 0.0 && jv[k] >= g.K) {
-                    const double q2 = HASW ? x * x / (double)iv[k] : x * x;
-                    accum_tail<CHECK>(g, jv[k], (double)opq(av[k]) * x, CHECK ? (double)opq(cv[k]) * x : 0.0, q2);
-                }
-            }
-        }
-    }
-    if (g.X) {
-#pragma unroll
-        for (int k = 0; k < P2; ++k) {
-            const int e = lane + 64 * k;
-            if (e < d) {
-                const double w = HASW ? (double)iv[k] * inv_g : inv_g;
-                g.X[g.perm[ib + e]] = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -888,30 +903,40 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
 // ---------------------------------------------------------------------------
 // the fused gradient kernel: one workgroup per chunk
 // ---------------------------------------------------------------------------
-// lane groups from batch entry r on; returns the first entry not processed
+// lane items from batch entry r on; returns the first entry not processed
 template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
 __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine, const int r, const int rn,
                                              const Item& it, const Lds& s, double gamma, Obj& ob)
 {
     // FP64 storage keeps blocks of at most 8 edges in lanes (register budget);
     // per-edge weights (and rows beyond LDS) need more registers, so their
-    // pipelined runs stop at smaller classes and their lane blocks at 16
-    // edges (the layout guarantees d <= CAP)
+    // pipelined runs stop at smaller classes and their one-lane blocks at 16
+    // edges (the layout guarantees d <= CAP for S = 1 and R <= RMAX for S > 1)
     constexpr bool W8 = sizeof(VT) == 8;
-    constexpr int PIPE = W8 ? 8 : (HASW ? 8 : (TAIL ? 12 : 16));
+    constexpr int RMAX = seg_rmax(W8, HASW, TAIL);
     constexpr int CAP = lane_cap(W8, HASW, TAIL);
-    switch (lane_class<VT>(it.d)) {
-    case 4: return lane_run<VT, CHECK, HASW, TAIL, BOX, 4>(g, mine, r, rn, s, gamma, ob);
-    case 8:
-        if constexpr (PIPE >= 8) return lane_run<VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
-        lane_group<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
-        return r + 1;
+    const int cls = lane_class<VT, HASW, TAIL>(it.d, it.lg);
+    if (it.lg == 2) {
+        if (cls == 8) return lane_run<4, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
+        return lane_run<4, VT, CHECK, HASW, TAIL, BOX, RMAX>(g, mine, r, rn, s, gamma, ob);
+    }
+    if (it.lg == 4) {
+        if (cls == 8) return lane_run<16, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
+        return lane_run<16, VT, CHECK, HASW, TAIL, BOX, RMAX>(g, mine, r, rn, s, gamma, ob);
+    }
+    if (it.lg == 6) {
+        if (cls == 8) return lane_run<64, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
+        return lane_run<64, VT, CHECK, HASW, TAIL, BOX, RMAX>(g, mine, r, rn, s, gamma, ob);
+    }
+    switch (cls) {
+    case 4: return lane_run<1, VT, CHECK, HASW, TAIL, BOX, 4>(g, mine, r, rn, s, gamma, ob);
+    case 8: return lane_run<1, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
     case 12:
-        if constexpr (PIPE >= 12) return lane_run<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
+        if constexpr (RMAX >= 12) return lane_run<1, VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
         lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, it, s, gamma, ob);
         return r + 1;
     case 16:
-        if constexpr (PIPE >= 16) return lane_run<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
+        if constexpr (RMAX >= 16) return lane_run<1, VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
         lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, it, s, gamma, ob);
         return r + 1;
     case 24:
@@ -921,17 +946,6 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
         if constexpr (CAP > 24) lane_group<VT, CHECK, HASW, TAIL, BOX, 32>(g, it, s, gamma, ob);
         return r + 1;
     }
-}
-
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
-__device__ __forceinline__ void wave_dispatch(const GradArgs& g, const Item& it, const Lds& s,
-                                              double gamma, Obj& ob)
-{
-    const int d = it.d;
-    if (d <= 64) wave_block<VT, CHECK, HASW, TAIL, BOX, 1>(g, it, s, gamma, ob);
-    else if (d <= 128) wave_block<VT, CHECK, HASW, TAIL, BOX, 2>(g, it, s, gamma, ob);
-    else if (d <= 256) wave_block<VT, CHECK, HASW, TAIL, BOX, 4>(g, it, s, gamma, ob);
-    else wave_block<VT, CHECK, HASW, TAIL, BOX, 8>(g, it, s, gamma, ob);
 }
 
 template <typename VT, bool CHECK, bool HASW, bool TAIL>
@@ -984,31 +998,23 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     const Chunk ch = g.chunks[chunk];
     Obj ob = {0.0, 0.0, 0.0};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // this chunk's share of the lane groups, then of the wave blocks (each
-    // kind is spread evenly over the chunks, so no chunk is left with a long
-    // run of the costlier wave blocks).  A wave takes items a0 + wave + r*kWaves;
-    // their descriptors arrive 64 at a time (lane r holds item r of the batch)
-    // and are broadcast with readlane, so a group waits on its data only.
-    for (int kind = 0; kind < 2; ++kind) {
-        const int i0 = kind == 0 ? ch.a0 : ch.w0;
-        const int i1 = kind == 0 ? ch.a1 : ch.w1;
+    // this chunk's share of the lane items: a wave takes items a0 + wave +
+    // r*kWaves; their descriptors arrive 64 at a time (lane r holds item r of
+    // the batch) and are broadcast with readlane, so a group waits on its
+    // data only
+    {
+        const int i0 = ch.a0, i1 = ch.a1;
         const int nmine = i1 - i0 > wave ? (i1 - i0 - wave + kWaves - 1) / kWaves : 0;
         for (int r0 = 0; r0 < nmine; r0 += 64) {
             const int lane = threadIdx.x & 63;
             const int my = i0 + wave + (r0 + lane) * kWaves;
-            Item mine = {0, 0, 0, 0, 0};
+            Item mine = {0, 0, 0, 0, 0, 0};
             if (r0 + lane < nmine) mine = g.items[my];
             const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
             for (int r = 0; r < rn;) {
                 const Item it = item_at(mine, r);
-                if (kind == 0) {
-                    if (it.proj == 1) r = lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, mine, r, rn, it, s, gamma, ob);
-                    else r = lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, mine, r, rn, it, s, gamma, ob);
-                } else {
-                    if (it.proj == 1) wave_dispatch<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-                    else wave_dispatch<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
-                    ++r;
-                }
+                if (it.proj == 1) r = lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, mine, r, rn, it, s, gamma, ob);
+                else r = lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, mine, r, rn, it, s, gamma, ob);
             }
         }
     }

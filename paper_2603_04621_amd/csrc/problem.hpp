@@ -16,7 +16,7 @@ struct dl_problem {
     int has_box = 0, has_w = 0, solve_ok = 1;
     int J = 0, K = 0;                  // rows; rows resident in LDS
     int nchunks = 0, nitems = 0, nblk2 = 0;
-    int64_t n_lane = 0, n_wave = 0, n_wg = 0;
+    int64_t n_lane = 0, n_seg = 0, n_wg = 0;
     int64_t stream_bytes = 0;
     size_t device_bytes = 0;
     // edge stream

@@ -120,15 +120,20 @@ def test_grad_tiny_uniform(O, dev, storage, gamma):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_grad_mixed_degrees_all_paths(O, dev, storage):
-    """Degrees 1..700: lane groups (<= 16), wave blocks (<= 512) and
-    workgroup blocks, simplex and box, several tiles and a ragged tail."""
+    """Degrees 1..1500: one-lane blocks, blocks on 4, 16 and 64 lanes (every
+    row class, full and compacted last rows) and workgroup blocks, simplex
+    and box, several groups per class and ragged last groups."""
     rng = np.random.default_rng(11)
-    deg = np.concatenate([rng.integers(1, 17, size=3000), rng.integers(17, 513, size=60),
-                          rng.integers(513, 700, size=6)])
+    deg = np.concatenate([rng.integers(1, 33, size=3000), rng.integers(33, 65, size=150),
+                          rng.integers(65, 257, size=60), rng.integers(257, 1025, size=16),
+                          rng.integers(1025, 1500, size=4)])
     rng.shuffle(deg)
-    inst = I._finish("mixed", 11, deg.size, 300, deg, rng, I.zipf_cdf(300, 1.1),
+    inst = I._finish("mixed", 11, deg.size, 2000, deg, rng, I.zipf_cdf(2000, 1.1),
                      I._neg_lognormal, I._lognormal_a, 0.3, box_frac=0.3, capacity="greedy",
                      seed_key=[11, 1])
+    with gpu_problem(inst, storage) as p:
+        info = p.info()
+    assert info["lane_groups"] > 0 and info["seg_groups"] > 0 and info["wg_blocks"] > 0
     for seed, gamma in ((1, 1e-2), (2, 1e-3)):
         compare(O, inst, storage, lam_for(inst, seed, 1.0), gamma)
 
@@ -142,6 +147,17 @@ def test_grad_heavy_tailed_mixed(O, dev):
     inst = I.heavy(I=20_000, J=4_000, dmax=4096, capacity="greedy")
     compare(O, inst, "f32", lam_for(inst, 4, 2.0), 1e-2)
     compare(O, inst, "bf16", lam_for(inst, 5, 2.0), 1e-2)
+
+
+def test_grad_heavy_tailed_rows_beyond_lds(O, dev):
+    """Heavy-tailed blocks on every lane width with more destinations than
+    LDS holds (the tail-row variant of each path)."""
+    inst = I.heavy(I=12_000, J=20_000, dmax=4096, capacity="greedy")
+    with gpu_problem(inst) as p:
+        info = p.info()
+    assert info["lds_rows"] < inst.m and info["seg_groups"] > 0 and info["wg_blocks"] > 0
+    compare(O, inst, "f32", lam_for(inst, 12, 2.0), 1e-2)
+    compare(O, inst, "f64", lam_for(inst, 13, 2.0), 1e-2, grad_tol=1e-5)
 
 
 def test_grad_rows_beyond_lds(O, dev):
