@@ -809,8 +809,8 @@ __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int
 }
 
 // ---------------------------------------------------------------------------
-// WG items: one workgroup per block of any degree; t is recomputed on every
-// pass (the block's data stays in L2 between passes)
+// WG items beyond 8 kWG edges: one workgroup per block of any degree, t
+// recomputed on every pass (the block's data stays in L2 between passes)
 // ---------------------------------------------------------------------------
 template <typename VT, bool CHECK, bool HASW, bool TAIL>
 __device__ __forceinline__ double edge_t(const GradArgs& g, const Lds& s, int64_t idx, double& w,
@@ -896,6 +896,110 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
             accum<CHECK, TAIL>(s, g, g.dst[idx], a * x, cx, q2);
         }
         if (g.X) g.X[g.perm[idx]] = x;
+    }
+    __syncthreads();
+}
+
+// WG items of up to kWG * RW edges with the block in registers: edge
+// e = k kWG + tid, k < RW; all loads issued at once (one memory round trip),
+// then the threshold by workgroup reductions (every thread gets the same
+// sums, so the loop is uniform across the workgroup).
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int RW>
+__device__ __forceinline__ void wg_block_reg(const GradArgs& g, const Item& it, const Lds& s, double gamma,
+                                             Obj& ob)
+{
+    using R = typename Val<VT>::reg;
+    const int d = uni(it.d);
+    const int64_t base = uni64(it.base);
+    const int tid = threadIdx.x;
+    const double inv_g = 1.0 / gamma;
+    const VT* __restrict__ A = (const VT*)g.A + base;
+    const VT* __restrict__ C = (const VT*)g.C + base;
+    const int32_t* __restrict__ Dst = g.dst + base;
+    VT ar[RW], cr[RW];
+    int jv[RW];
+    float uv[BOX ? RW : 1], wv[HASW ? RW : 1];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int e = k * kWG + tid;
+        const uint32_t off = (uint32_t)(e < d ? e : d - 1);
+        ar[k] = ldo(A, off);
+        cr[k] = ldo(C, off);
+        jv[k] = ldo(Dst, off);
+        if (BOX) uv[k] = ldo(g.U + base, off);
+        if (HASW) wv[k] = ldo(g.IV + base, off);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double t[RW];
+    R av[RW], cv[CHECK ? RW : 1];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        av[k] = Val<VT>::cvt(ar[k]);
+        const R c = Val<VT>::cvt(cr[k]);
+        const double tk = -((double)c + (double)av[k] * get_lam<CHECK, TAIL>(s, g, jv[k]));
+        t[k] = k * kWG + tid < d ? tk : -INFINITY;
+        if (CHECK) cv[k] = c;
+    }
+    double tau = 0.0;
+    if (!BOX) {
+        double s0 = 0.0, mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+            const double z = w * t[k];
+            s0 += z > 0.0 ? z : 0.0;
+            mx = fmax(mx, t[k] - 1.0 / w);
+        }
+        wg_sum_max(s0, mx, s.red);
+        if (s0 > 1.0) {
+            tau = mx > 0.0 ? mx : 0.0;
+            double sw = 0.0, swt = 0.0;
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+                const bool in = t[k] > tau;
+                sw += in ? w : 0.0;
+                swt += in ? w * t[k] : 0.0;
+                n += in ? 1 : 0;
+            }
+            wg_sum3(sw, swt, n, s.red);
+#pragma unroll 1
+            for (int rep = 0; rep < 2 * d + 4; ++rep) {
+                const double tn = (swt - 1.0) / sw;
+                double sw2 = 0.0, swt2 = 0.0;
+                int n2 = 0;
+#pragma unroll
+                for (int k = 0; k < RW; ++k) {
+                    const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+                    const bool in = t[k] > tn;
+                    sw2 += in ? w : 0.0;
+                    swt2 += in ? w * t[k] : 0.0;
+                    n2 += in ? 1 : 0;
+                }
+                wg_sum3(sw2, swt2, n2, s.red);
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                sw = sw2;
+                swt = swt2;
+                n = n2;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+        const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+        if (x != 0.0) {
+            const double q2 = HASW ? x * x / (double)wv[k] : x * x;
+            ob.ot += t[k] * x;
+            ob.oq += q2;
+            const double cx = CHECK ? (double)cv[k] * x : 0.0;
+            if (CHECK) ob.oc += cx;
+            accum<CHECK, TAIL>(s, g, jv[k], (double)av[k] * x, cx, q2);
+        }
+        const int e = k * kWG + tid;
+        if (g.X && e < d) g.X[g.perm[base + e]] = x;
     }
     __syncthreads();
 }
@@ -1020,8 +1124,18 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     }
     for (int i = ch.b0; i < ch.b1; ++i) {
         const Item it = g.items[i];
-        if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-        else wg_block<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+        const int d = uni(it.d);
+        if (it.proj == 1) {
+            if (d <= 2 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, true, 2>(g, it, s, gamma, ob);
+            else if (d <= 4 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, true, 4>(g, it, s, gamma, ob);
+            else if (d <= 8 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, true, 8>(g, it, s, gamma, ob);
+            else wg_block<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
+        } else {
+            if (d <= 2 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, false, 2>(g, it, s, gamma, ob);
+            else if (d <= 4 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, false, 4>(g, it, s, gamma, ob);
+            else if (d <= 8 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, false, 8>(g, it, s, gamma, ob);
+            else wg_block<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+        }
     }
     __syncthreads();
 
