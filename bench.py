@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the work layout by timing candidates on a sample at create")
     ap.add_argument("--cache", default=None,
                     help="directory to save/load the generated instance (npy files)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -270,9 +272,10 @@ def main():
     inst = load_or_generate(I, args)
     log(f"instance with {inst.n} nnz ready in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    prob = Problem(inst, storage=args.storage)
+    prob = Problem(inst, storage=args.storage, autotune=args.autotune)
     info = prob.info()
-    log(f"created in {time.perf_counter() - t0:.1f}s: {info}")
+    create_s = time.perf_counter() - t0
+    log(f"created in {create_s:.1f}s: {info}")
 
     gamma = 1e-3
     # the solve the steps belong to: one gamma stage at the final gamma, the
@@ -336,6 +339,10 @@ def main():
                      "kernel": "grad_kernel, ordinary iterations (fused gather + projection + per-destination sums)"},
         "final_g": r.g,
         "final_rel_gap": r.rel_gap,
+        "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks", "chunks",
+                                        "lds_rows", "lane_cap", "seg_rmax", "chunks_per_cu",
+                                        "tuned")},
+        "create_seconds": create_s,
     }
     if not args.no_binding:
         # same sparsity and values with the paper's greedy-load capacities
@@ -345,7 +352,7 @@ def main():
         inst_b = I.Instance(inst.m, inst.n, inst.dst, inst.a, inst.c, lam_b, inst.block_off,
                             inst.block_proj, inst.upper, args.config + "-binding", inst.seed)
         prob.close()
-        with Problem(inst_b, storage=args.storage) as pb:
+        with Problem(inst_b, storage=args.storage, autotune=args.autotune) as pb:
             _, rb, elb = timed(pb)
         out["binding_variant"] = {
             "capacity": "greedy load (Appendix B)", "iter_per_s": args.steps / elb,

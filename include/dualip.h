@@ -99,15 +99,26 @@ typedef struct {
  *   primal_scale   0: v = 1; 1: v_e = |A_{:,e}|_2 (the column-norm choice of
  *                  Section 5, "Primal scaling"); 2: v given in `v`.
  *   v              [n] host array of positive scales when primal_scale = 2.
+ *   autotune       0 (default): the work layout follows the kernel variant's
+ *                  register budget (largest one-lane blocks, rows per lane,
+ *                  one workgroup per compute unit).  1: before building the
+ *                  problem, time the gradient kernel on a sample of its blocks
+ *                  (every k-th block, about 16M nonzeros, same destinations)
+ *                  for each candidate layout (smaller one-lane blocks, fewer
+ *                  rows per lane, two workgroups per compute unit) at lambda =
+ *                  0 and keep the fastest; costs a few sample builds at create.
  * The regularizer is gamma/2 sum_e v_e^2 x_e^2 (view (i) of primal scaling). */
 typedef struct {
     dl_storage storage;
     int32_t row_normalize;
     int32_t primal_scale;
     const double* v;
+    int32_t autotune;
+    int32_t reserved;        /* set to 0 */
 } dl_problem_opts;
 
-/* Fills opts with the defaults (DL_F32, row_normalize = 1, primal_scale = 0). */
+/* Fills opts with the defaults (DL_F32, row_normalize = 1, primal_scale = 0,
+ * autotune = 0). */
 void dl_problem_opts_init(dl_problem_opts* opts);
 
 /* Host-only validation of desc/opts with the rules above; no device is
@@ -251,6 +262,10 @@ typedef struct {
     int64_t stream_bytes;      /* per-nonzero bytes streamed by one gradient pass */
     int64_t device_bytes;      /* device memory held by the problem              */
     int32_t storage, has_box;
+    int32_t lane_cap;          /* largest degree of one-lane blocks               */
+    int32_t seg_rmax;          /* largest rows per lane of multi-lane blocks      */
+    int32_t chunks_per_cu;     /* workgroups of the gradient kernel per CU        */
+    int32_t tuned;             /* 1 when the layout was picked by autotune        */
 } dl_problem_info;
 dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info);
 

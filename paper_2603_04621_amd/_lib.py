@@ -38,7 +38,7 @@ class ProblemDesc(ctypes.Structure):
 
 class ProblemOpts(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int), ("row_normalize", c_i32), ("primal_scale", c_i32),
-                ("v", c_ptr)]
+                ("v", c_ptr), ("autotune", c_i32), ("reserved", c_i32)]
 
 
 class Eval(ctypes.Structure):
@@ -65,7 +65,8 @@ class SolveResult(ctypes.Structure):
 class ProblemInfo(ctypes.Structure):
     _fields_ = [(k, c_i64) for k in ("m", "n", "num_blocks", "lane_groups", "seg_groups",
                                      "wg_blocks", "chunks", "lds_rows", "stream_bytes",
-                                     "device_bytes")] + [("storage", c_i32), ("has_box", c_i32)]
+                                     "device_bytes")] + [(k, c_i32) for k in (
+                    "storage", "has_box", "lane_cap", "seg_rmax", "chunks_per_cu", "tuned")]
 
 
 # every symbol include/dualip.h declares

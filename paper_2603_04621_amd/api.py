@@ -55,12 +55,14 @@ class _HostDesc:
                                   _np_ptr(self.upper))
 
 
-def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: int = 0, v=None):
+def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: int = 0, v=None,
+              autotune: bool = False):
     o = L.ProblemOpts()
     L.lib().dl_problem_opts_init(ctypes.byref(o))
     o.storage = L.STORAGE[storage]
     o.row_normalize = 1 if row_normalize else 0
     o.primal_scale = int(primal_scale)
+    o.autotune = 1 if autotune else 0
     keep = None
     if v is not None:
         keep = np.ascontiguousarray(v, dtype=np.float64)
@@ -136,12 +138,13 @@ class Problem:
     """A matching LP created on the current HIP device (dl_problem_create)."""
 
     def __init__(self, inst, storage: str = "f32", row_normalize: bool = True,
-                 primal_scale: int = 0, v=None, layout: str = "csc", stream=None):
+                 primal_scale: int = 0, v=None, layout: str = "csc", stream=None,
+                 autotune: bool = False):
         import torch
         self.m, self.n = int(inst.m), int(inst.n)
         self.device = torch.device("cuda", torch.cuda.current_device())
         hd = _HostDesc(inst, layout)
-        o, _keep = make_opts(storage, row_normalize, primal_scale, v)
+        o, _keep = make_opts(storage, row_normalize, primal_scale, v, autotune)
         h = ctypes.c_void_p()
         L.check(L.lib().dl_problem_create(ctypes.byref(hd.desc), ctypes.byref(o),
                                           _stream(stream), ctypes.byref(h)), "dl_problem_create")

@@ -76,6 +76,8 @@ extern "C" void dl_problem_opts_init(dl_problem_opts* o)
     o->row_normalize = 1;
     o->primal_scale = 0;
     o->v = nullptr;
+    o->autotune = 0;
+    o->reserved = 0;
 }
 
 extern "C" void dl_solve_opts_init(dl_solve_opts* o)
@@ -380,22 +382,26 @@ static void free_problem(dl_problem* p)
     delete p;
 }
 
-extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_problem_opts* opts_in,
-                                       void* hip_stream, dl_problem** out)
-{
-    if (!out) { set_error("out is NULL"); return DL_ERR_INVALID_ARG; }
-    *out = nullptr;
-    dl_problem_opts opts;
-    dl_problem_opts_init(&opts);
-    if (opts_in) opts = *opts_in;
-    int solve_ok = 1;
-    dl_status st = validate_impl(d, &opts, &solve_ok);
-    if (st != DL_OK) return st;
-    hipStream_t s = (hipStream_t)hip_stream;
+// Work layout of a problem: largest one-lane degree and rows per lane (each
+// clamped to the kernel variant's register budget) and workgroups per CU.
+struct LayoutChoice {
+    int lane_cap = 1 << 30, seg_rmax = 1 << 30, chunk_mult = 1, tuned = 0;
+};
 
+static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& opts, hipStream_t s,
+                             LayoutChoice* out);
+
+// builds and uploads a validated problem with the given layout
+static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& opts, int solve_ok,
+                             const LayoutChoice& lc, hipStream_t s, dl_problem** out)
+{
+    dl_status st = DL_OK;
     const int64_t m = d->m, n = d->n;
     dl_problem* p = new dl_problem();
-    HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
+    {
+        const hipError_t e = hipGetDevice(&p->device);
+        if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+    }
     p->m = m;
     p->n = n;
     p->nblocks = d->num_blocks;
@@ -448,13 +454,17 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
 
     // work items and chunks
     const int cus = device_cus(p->device);
-    int nch = (int)std::min<int64_t>(cus, std::max<int64_t>(1, (n + 32767) / 32768));
+    int nch = (int)std::min<int64_t>((int64_t)cus * lc.chunk_mult, std::max<int64_t>(1, (n + 32767) / 32768));
     HostLayout L;
     const size_t max_lds = device_max_lds(p->device);
     int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
     p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
     const bool f64 = opts.storage == DL_F64, tail = p->K < m;
-    build_items(d, nch, lane_cap(f64, p->has_w != 0, tail), seg_rmax(f64, p->has_w != 0, tail), L);
+    p->lane_cap = std::min(lc.lane_cap, lane_cap(f64, p->has_w != 0, tail));
+    p->seg_rmax = std::min(lc.seg_rmax, seg_rmax(f64, p->has_w != 0, tail));
+    p->chunk_mult = lc.chunk_mult;
+    p->tuned = lc.tuned;
+    build_items(d, nch, p->lane_cap, p->seg_rmax, L);
     p->nchunks = nch;
     p->nitems = (int)L.items.size();
     p->n_lane = L.n_lane;
@@ -558,6 +568,133 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     return DL_OK;
 }
 
+// Autotune: every k-th block of the problem (about kTuneNnz nonzeros, all m
+// destinations, same projection types and scales) is built with each
+// candidate layout and the fused gradient timed at lambda = 0, gamma = 1e-3
+// (median of 5 launches after 2 warm-up launches); the fastest wins.
+constexpr int64_t kTuneNnz = (int64_t)16 << 20;
+
+static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& opts, hipStream_t s,
+                             LayoutChoice* out)
+{
+    const int64_t I = d->num_blocks, n = d->n;
+    const int64_t step = std::max<int64_t>(1, (n + kTuneNnz - 1) / kTuneNnz);
+    // sample columns, one CSC entry each
+    std::vector<int32_t> crow((size_t)n, 0);
+    std::vector<double> cval((size_t)n, 0.0);
+    if (d->layout == DL_CSC) {
+        for (int64_t e = 0; e < n; ++e) {
+            const int64_t lo = d->ptr ? d->ptr[e] : e, hi = d->ptr ? d->ptr[e + 1] : e + 1;
+            if (hi > lo) { crow[e] = d->idx[lo]; cval[e] = d->val[lo]; }
+        }
+    } else {
+        for (int64_t j = 0; j < d->m; ++j)
+            for (int64_t k = d->ptr[j]; k < d->ptr[j + 1]; ++k) { crow[d->idx[k]] = (int32_t)j; cval[d->idx[k]] = d->val[k]; }
+    }
+    std::vector<int64_t> off(1, 0);
+    std::vector<uint8_t> proj;
+    std::vector<int32_t> idx;
+    std::vector<double> val, c, up, v;
+    for (int64_t i = 0; i < I; i += step) {
+        for (int64_t e = d->block_off[i]; e < d->block_off[i + 1]; ++e) {
+            idx.push_back(crow[e]);
+            val.push_back(cval[e]);
+            c.push_back(d->c[e]);
+            if (d->upper) up.push_back(d->upper[e]);
+            if (opts.primal_scale == 2) v.push_back(opts.v[e]);
+        }
+        off.push_back((int64_t)idx.size());
+        proj.push_back(d->block_proj[i]);
+    }
+    dl_problem_desc sd = *d;
+    sd.n = sd.nnz = (int64_t)idx.size();
+    sd.layout = DL_CSC;
+    sd.ptr = nullptr;
+    sd.idx = idx.data();
+    sd.val = val.data();
+    sd.c = c.data();
+    sd.num_blocks = (int64_t)proj.size();
+    sd.block_off = off.data();
+    sd.block_proj = proj.data();
+    sd.upper = d->upper ? up.data() : nullptr;
+    dl_problem_opts so = opts;
+    so.autotune = 0;
+    so.v = opts.primal_scale == 2 ? v.data() : nullptr;
+
+    double* lam = nullptr;
+    HIP_TRY(hipMalloc(&lam, (size_t)d->m * sizeof(double)), "tuning buffer");
+    dl_status st = DL_OK;
+    {
+        const hipError_t e = hipMemsetAsync(lam, 0, (size_t)d->m * sizeof(double), s);
+        if (e != hipSuccess) st = hip_fail(e, "tuning buffer");
+    }
+    // candidates: the variant's budget, smaller one-lane blocks, fewer rows
+    // per lane, two workgroups per CU
+    std::vector<LayoutChoice> cands;
+    for (int lcap : {1 << 30, 16})
+        for (int rmax : {1 << 30, 8})
+            for (int mult : {1, 2}) {
+                LayoutChoice c;
+                c.lane_cap = lcap;
+                c.seg_rmax = rmax;
+                c.chunk_mult = mult;
+                c.tuned = 1;
+                cands.push_back(c);
+            }
+    double best = INFINITY;
+    LayoutChoice pick = cands[0];
+    std::vector<std::pair<int, int>> seen;
+    for (size_t q = 0; q < cands.size() && st == DL_OK; ++q) {
+        dl_problem* sp = nullptr;
+        st = create_with(&sd, so, 1, cands[q], s, &sp);
+        if (st != DL_OK) break;
+        // layouts that clamp to one already timed are skipped
+        const std::pair<int, int> key(sp->lane_cap * 1000 + sp->seg_rmax, sp->chunk_mult);
+        if (std::find(seen.begin(), seen.end(), key) == seen.end()) {
+            seen.push_back(key);
+            double ms = 0.0;
+            std::vector<double> t;
+            st = dl_time_grad_kernel(sp, lam, 1e-3, 2, 0, &ms, s);
+            for (int r = 0; r < 5 && st == DL_OK; ++r) {
+                st = dl_time_grad_kernel(sp, lam, 1e-3, 1, 0, &ms, s);
+                t.push_back(ms);
+            }
+            if (st == DL_OK) {
+                std::sort(t.begin(), t.end());
+                if (t[t.size() / 2] < best) {
+                    best = t[t.size() / 2];
+                    pick = cands[q];
+                }
+            }
+        }
+        dl_problem_destroy(sp);
+    }
+    (void)hipFree(lam);
+    if (st == DL_OK) *out = pick;
+    return st;
+}
+
+extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_problem_opts* opts_in,
+                                       void* hip_stream, dl_problem** out)
+{
+    if (!out) { set_error("out is NULL"); return DL_ERR_INVALID_ARG; }
+    *out = nullptr;
+    dl_problem_opts opts;
+    dl_problem_opts_init(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.autotune != 0 && opts.autotune != 1) { set_error("autotune must be 0 or 1"); return DL_ERR_INVALID_ARG; }
+    int solve_ok = 1;
+    dl_status st = validate_impl(d, &opts, &solve_ok);
+    if (st != DL_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    LayoutChoice lc;
+    if (opts.autotune) {
+        st = tune_layout(d, opts, s, &lc);
+        if (st != DL_OK) return st;
+    }
+    return create_with(d, opts, solve_ok, lc, s, out);
+}
+
 extern "C" dl_status dl_problem_destroy(dl_problem* p)
 {
     if (!p) return DL_OK;
@@ -581,6 +718,10 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* i
     info->device_bytes = (int64_t)p->device_bytes;
     info->storage = p->storage;
     info->has_box = p->has_box;
+    info->lane_cap = p->lane_cap;
+    info->seg_rmax = p->seg_rmax;
+    info->chunks_per_cu = p->chunk_mult;
+    info->tuned = p->tuned;
     return DL_OK;
 }
 

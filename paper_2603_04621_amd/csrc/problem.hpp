@@ -17,6 +17,7 @@ struct dl_problem {
     int J = 0, K = 0;                  // rows; rows resident in LDS
     int nchunks = 0, nitems = 0, nblk2 = 0;
     int64_t n_lane = 0, n_seg = 0, n_wg = 0;
+    int lane_cap = 0, seg_rmax = 0, chunk_mult = 1, tuned = 0;   // work layout
     int64_t stream_bytes = 0;
     size_t device_bytes = 0;
     // edge stream

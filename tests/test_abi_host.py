@@ -133,3 +133,18 @@ def test_solve_opts_defaults():
     assert o.gamma0 == 0.01 and o.max_step == o.gamma0
     assert o.init_step == pytest.approx(1e-2 * o.gamma0)
     assert o.check_every == 10 and o.momentum == 1 and o.adaptive == 1
+
+
+def test_problem_opts_defaults_and_autotune_flag():
+    """Defaults leave autotune off; a value other than 0 or 1 is rejected
+    before any device work (so this runs without a GPU)."""
+    o, _ = api.make_opts()
+    assert o.storage == L.STORAGE["f32"] and o.row_normalize == 1 and o.primal_scale == 0
+    assert o.autotune == 0 and o.reserved == 0
+    inst = I.tiny()
+    hd = api._HostDesc(inst, "csc")
+    o.autotune = 2
+    h = ctypes.c_void_p()
+    st = L.lib().dl_problem_create(ctypes.byref(hd.desc), ctypes.byref(o), None, ctypes.byref(h))
+    assert st == L.DL_ERR_INVALID_ARG and not h.value
+    assert "autotune" in L.lib().dl_last_error().decode()

@@ -41,7 +41,7 @@ def gpu_problem(inst, storage="f32", **kw):
 
 
 def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc", v=None,
-            primal_scale=0):
+            primal_scale=0, autotune=False):
     """Runs one evaluation on both sides; returns the measured errors."""
     ref_inst = inst.rounded(storage)
     vv = None
@@ -55,7 +55,8 @@ def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc
         # the device keeps 1/v^2 in float32
         v_dev = 1.0 / np.sqrt((1.0 / vv ** 2).astype(np.float32).astype(np.float64))
     ev = O.dual_eval(ref_inst, lam, gamma, v=v_dev)
-    with gpu_problem(inst, storage, layout=layout, primal_scale=primal_scale, v=v) as p:
+    with gpu_problem(inst, storage, layout=layout, primal_scale=primal_scale, v=v,
+                     autotune=autotune) as p:
         grad, x, e = p.dual_grad(torch.from_numpy(lam), gamma, want_x=True, want_eval=True)
         grad = grad.cpu().numpy()
         x = x.cpu().numpy()
@@ -173,6 +174,17 @@ def test_grad_rows_beyond_lds(O, dev):
     assert info["lds_rows"] < inst.m
     compare(O, inst, "f32", lam_for(inst, 6, 2.0), 1e-3)
     compare(O, inst, "f64", lam_for(inst, 7, 2.0), 1e-2, grad_tol=1e-5)
+
+
+def test_autotuned_layout_matches_oracle(O, dev):
+    """A problem built with autotune (candidate layouts timed on a sample of
+    its blocks) reports the chosen layout and gives the oracle's gradient."""
+    inst = I.heavy(I=12_000, J=3_000, dmax=2048, capacity="greedy")
+    with gpu_problem(inst, "f32", autotune=True) as p:
+        info = p.info()
+    assert info["tuned"] == 1 and info["chunks_per_cu"] in (1, 2)
+    assert info["lane_cap"] in (16, 32) and info["seg_rmax"] in (8, 16)
+    compare(O, inst, "f32", lam_for(inst, 14, 2.0), 1e-2, autotune=True)
 
 
 def test_grad_csr_equals_csc(O, dev):
