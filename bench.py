@@ -33,7 +33,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("grad_impl.hpp", "common.hpp", "kernels.hpp"):
+    for f in ("grad_impl.hpp", "lanes.hpp", "common.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2603_04621_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

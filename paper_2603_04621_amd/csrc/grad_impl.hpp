@@ -26,6 +26,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "lanes.hpp"
 
 namespace dl {
 
@@ -75,28 +76,6 @@ template <typename T>
 __device__ __forceinline__ T ldo(const T* base, uint32_t elem)
 {
     return *(const T*)((const char*)base + elem * (uint32_t)sizeof(T));
-}
-
-// ---------------------------------------------------------------------------
-// wave / workgroup reductions (butterfly: every lane ends with the same bits)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_sum_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 // wave-uniform copies (scalar registers) of values the compiler cannot prove uniform
@@ -318,27 +297,21 @@ __device__ __forceinline__ bool seg_valid(const SegGeo& q, int k)
     return b < q.nb && (k < q.R - 1 || (k == q.R - 1 && s < q.rem));
 }
 
-// butterfly reductions over the S lanes of a segment
+// reductions over the S lanes of a segment
 template <int S>
 __device__ __forceinline__ double seg_sum(double v)
 {
-#pragma unroll
-    for (int o = 1; o < S; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return grp_sum<S>(v);
 }
 template <int S>
 __device__ __forceinline__ double seg_max(double v)
 {
-#pragma unroll
-    for (int o = 1; o < S; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return grp_max<S>(v);
 }
 template <int S>
 __device__ __forceinline__ int seg_sum_i(int v)
 {
-#pragma unroll
-    for (int o = 1; o < S; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return grp_sum_i<S>(v);
 }
 
 // stored values of rows k < P, as loaded
@@ -901,51 +874,60 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
 }
 
 // WG items of up to kWG * RW edges with the block in registers: edge
-// e = k kWG + tid, k < RW; all loads issued at once (one memory round trip),
-// then the threshold by workgroup reductions (every thread gets the same
-// sums, so the loop is uniform across the workgroup).
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int RW>
-__device__ __forceinline__ void wg_block_reg(const GradArgs& g, const Item& it, const Lds& s, double gamma,
-                                             Obj& ob)
+// e = k kWG + tid, k < RW; all loads of a block issued at once, then the
+// threshold by workgroup reductions (every thread gets the same sums, so the
+// loop is uniform across the workgroup).  Runs of blocks of one class are
+// pipelined like the lane runs: the next block's loads are in flight while
+// the current block is reduced.
+template <int RW, typename VT, bool BOX, bool HASW>
+__device__ __forceinline__ void wg_load(const GradArgs& g, const int64_t base, const int d,
+                                        LaneRaw<VT, BOX, HASW, RW>& r)
 {
-    using R = typename Val<VT>::reg;
-    const int d = uni(it.d);
-    const int64_t base = uni64(it.base);
-    const int tid = threadIdx.x;
-    const double inv_g = 1.0 / gamma;
     const VT* __restrict__ A = (const VT*)g.A + base;
     const VT* __restrict__ C = (const VT*)g.C + base;
     const int32_t* __restrict__ Dst = g.dst + base;
-    VT ar[RW], cr[RW];
-    int jv[RW];
-    float uv[BOX ? RW : 1], wv[HASW ? RW : 1];
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-        const int e = k * kWG + tid;
+        const int e = k * kWG + (int)threadIdx.x;
         const uint32_t off = (uint32_t)(e < d ? e : d - 1);
-        ar[k] = ldo(A, off);
-        cr[k] = ldo(C, off);
-        jv[k] = ldo(Dst, off);
-        if (BOX) uv[k] = ldo(g.U + base, off);
-        if (HASW) wv[k] = ldo(g.IV + base, off);
+        r.a[k] = ldo(A, off);
+        r.c[k] = ldo(C, off);
+        r.j[k] = ldo(Dst, off);
+        if (BOX) r.u[k] = ldo(g.U + base, off);
+        if (HASW) r.w[k] = ldo(g.IV + base, off);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    double t[RW];
-    R av[RW], cv[CHECK ? RW : 1];
+}
+
+template <int RW, typename VT, bool CHECK, bool BOX, bool HASW>
+__device__ __forceinline__ void wg_t(const int d, const LaneRaw<VT, BOX, HASW, RW>& r, const double (&lam)[RW],
+                                     LaneVals<VT, CHECK, BOX, HASW, RW>& v)
+{
+    using R = typename Val<VT>::reg;
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-        av[k] = Val<VT>::cvt(ar[k]);
-        const R c = Val<VT>::cvt(cr[k]);
-        const double tk = -((double)c + (double)av[k] * get_lam<CHECK, TAIL>(s, g, jv[k]));
-        t[k] = k * kWG + tid < d ? tk : -INFINITY;
-        if (CHECK) cv[k] = c;
+        v.a[k] = Val<VT>::cvt(r.a[k]);
+        const R c = Val<VT>::cvt(r.c[k]);
+        v.j[k] = r.j[k];
+        if (BOX) v.u[k] = r.u[k];
+        if (HASW) v.w[k] = r.w[k];
+        const double tk = -((double)c + (double)v.a[k] * lam[k]);
+        v.t[k] = k * kWG + (int)threadIdx.x < d ? tk : -INFINITY;
+        if (CHECK) v.c[k] = c;
     }
+}
+
+template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+__device__ __forceinline__ void wg_project(const GradArgs& g, const Lds& s, const int64_t base, const int d,
+                                           const double gamma, Obj& ob, const LaneVals<VT, CHECK, BOX, HASW, RW>& v)
+{
+    const double inv_g = 1.0 / gamma;
+    const double* t = v.t;
     double tau = 0.0;
     if (!BOX) {
         double s0 = 0.0, mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
-            const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+            const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
             const double z = w * t[k];
             s0 += z > 0.0 ? z : 0.0;
             mx = fmax(mx, t[k] - 1.0 / w);
@@ -957,7 +939,7 @@ __device__ __forceinline__ void wg_block_reg(const GradArgs& g, const Item& it, 
             int n = 0;
 #pragma unroll
             for (int k = 0; k < RW; ++k) {
-                const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+                const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
                 const bool in = t[k] > tau;
                 sw += in ? w : 0.0;
                 swt += in ? w * t[k] : 0.0;
@@ -971,7 +953,7 @@ __device__ __forceinline__ void wg_block_reg(const GradArgs& g, const Item& it, 
                 int n2 = 0;
 #pragma unroll
                 for (int k = 0; k < RW; ++k) {
-                    const double w = HASW ? (double)wv[k] * inv_g : inv_g;
+                    const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
                     const bool in = t[k] > tn;
                     sw2 += in ? w : 0.0;
                     swt2 += in ? w * t[k] : 0.0;
@@ -988,20 +970,74 @@ __device__ __forceinline__ void wg_block_reg(const GradArgs& g, const Item& it, 
     }
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-        const double w = HASW ? (double)wv[k] * inv_g : inv_g;
-        const double x = xval<BOX>(t[k], w, tau, BOX ? uv[k] : 0.0f);
+        const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
+        const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
         if (x != 0.0) {
-            const double q2 = HASW ? x * x / (double)wv[k] : x * x;
+            const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
             ob.ot += t[k] * x;
             ob.oq += q2;
-            const double cx = CHECK ? (double)cv[k] * x : 0.0;
+            const double cx = CHECK ? (double)v.c[k] * x : 0.0;
             if (CHECK) ob.oc += cx;
-            accum<CHECK, TAIL>(s, g, jv[k], (double)av[k] * x, cx, q2);
+            accum<CHECK, TAIL>(s, g, v.j[k], (double)v.a[k] * x, cx, q2);
         }
-        const int e = k * kWG + tid;
+        const int e = k * kWG + (int)threadIdx.x;
         if (g.X && e < d) g.X[g.perm[base + e]] = x;
     }
+}
+
+__device__ __forceinline__ int wg_class(int d) { return d <= 2 * kWG ? 2 : d <= 4 * kWG ? 4 : 8; }
+
+// WG items i, i+1, ... of class RW and one projection type; returns the first
+// item not processed
+template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+__device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, const Lds& s, double gamma, Obj& ob)
+{
+    constexpr bool EARLY = !CHECK && !TAIL;
+    Item it = g.items[i];
+    int64_t base = uni64(it.base);
+    int d = uni(it.d);
+    LaneRaw<VT, BOX, HASW, RW> cur;
+    wg_load<RW>(g, base, d, cur);
+#pragma unroll 1
+    for (;;) {
+        bool more = false;
+        int64_t bn = base;
+        int dn = d;
+        if (i + 1 < i1) {
+            const Item nx = g.items[i + 1];
+            const int nd = uni(nx.d);
+            if ((nx.proj == 1) == BOX && nd <= 8 * kWG && wg_class(nd) == RW) {
+                more = true;
+                bn = uni64(nx.base);
+                dn = nd;
+            }
+        }
+        LaneRaw<VT, BOX, HASW, RW> nxt;
+        LaneVals<VT, CHECK, BOX, HASW, RW> v;
+        double lam[RW];
+        __builtin_amdgcn_sched_barrier(0);
+        if (EARLY) {
+            wg_load<RW>(g, bn, dn, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < RW; ++k) lam[k] = get_lam<CHECK, TAIL>(s, g, cur.j[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < RW; ++k) lam[k] = get_lam<CHECK, TAIL>(s, g, cur.j[k]);
+            __builtin_amdgcn_sched_barrier(0);
+            wg_load<RW>(g, bn, dn, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        wg_t<RW>(d, cur, lam, v);
+        wg_project<RW, VT, CHECK, HASW, TAIL, BOX>(g, s, base, d, gamma, ob, v);
+        if (!more) break;
+        cur = nxt;
+        base = bn;
+        d = dn;
+        ++i;
+    }
     __syncthreads();
+    return i + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1122,19 +1158,24 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             }
         }
     }
-    for (int i = ch.b0; i < ch.b1; ++i) {
+    for (int i = ch.b0; i < ch.b1;) {
         const Item it = g.items[i];
         const int d = uni(it.d);
-        if (it.proj == 1) {
-            if (d <= 2 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, true, 2>(g, it, s, gamma, ob);
-            else if (d <= 4 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, true, 4>(g, it, s, gamma, ob);
-            else if (d <= 8 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, true, 8>(g, it, s, gamma, ob);
-            else wg_block<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-        } else {
-            if (d <= 2 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, false, 2>(g, it, s, gamma, ob);
-            else if (d <= 4 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, false, 4>(g, it, s, gamma, ob);
-            else if (d <= 8 * kWG) wg_block_reg<VT, CHECK, HASW, TAIL, false, 8>(g, it, s, gamma, ob);
+        if (d > 8 * kWG) {
+            if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
             else wg_block<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+            ++i;
+            continue;
+        }
+        const int rw = wg_class(d);
+        if (it.proj == 1) {
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, true>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, true>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, true>(g, i, ch.b1, s, gamma, ob);
+        } else {
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, false>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, false>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, false>(g, i, ch.b1, s, gamma, ob);
         }
     }
     __syncthreads();

@@ -1,49 +1,18 @@
-// HIP kernels of libdualip for CDNA4 (gfx950): the per-destination reduction,
-// the ascent step and small helpers.  The fused gradient kernel lives in
-// grad_impl.hpp (instantiated per storage type).
-//
-// The hot path is one fused pass over the edge stream per dual-gradient
-// evaluation (Section 3.1, Danskin): gather lam for each edge's destination,
-// t_e = -(c_e + a_e lam_j(e)) in FP64, project each source block onto its
-// simple set (Eq.(4),(5) simplex or box), and accumulate a_e x_e into the
-// per-destination sums of A x.  Nothing per-edge is written back.  The work is
-// sparse and bandwidth-bound, so it runs on the vector ALUs; no MFMA.
-//
-// Simplex threshold.  With w_e = 1/(gamma v_e^2) the block solution is
-// x_e = max(0, w_e (t_e - tau)), tau = 0 when sum_e max(0, w_e t_e) <= 1, else
-// the root of sum_e max(0, w_e (t_e - tau)) = 1.  Since x_e <= 1 forces
-// tau >= t_e - 1/w_e, the search starts at tau_0 = max(0, max_e (t_e - 1/w_e)),
-// whose set S_0 = {t > tau_0} holds every active edge.  Then the fixed point
-// tau <- (sum_S w t - 1) / sum_S w with S = {t > tau} (Michelot 1986) rises
-// monotonically and stops when S no longer shrinks; the result is exact (KKT
-// hold for the final set), not limited by a bisection tolerance.  Because
-// tau_1 > tau_0 (the top edge alone already gives w (t - tau_0) = 1) every
-// set along the way is a threshold set {t > tau}, so no membership mask is
-// kept.
+// HIP kernels of libdualip for CDNA4 (gfx950) other than the fused gradient
+// (grad_impl.hpp, instantiated per storage type): the per-destination
+// combination of the chunk partial sums, the FP64 scalar reductions, the
+// accelerated ascent step (Appendix B) with its stop test and gamma stages
+// (Section 5), and small helpers.  Their work is O(m); the O(nnz) pass is the
+// gradient kernel.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "lanes.hpp"
 
 namespace dl {
-
-// ---------------------------------------------------------------------------
-// shared helpers (the gradient kernel has its own copies in grad_impl.hpp)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 template <typename VT>
 hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s);
