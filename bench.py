@@ -52,25 +52,50 @@ def measured_traffic(workload_key: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0):
+def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0, gpu_evals=None):
     """The FP64 oracle's dual evaluation on this host, single-threaded, on a
     bounded sample: whole-instance evaluations while the budget lasts (at
-    least one)."""
+    least one).  With gpu_evals ({storage: (g, grad)} at the same lam), the
+    same oracle evaluations also state each storage's error: against the
+    oracle on the identically rounded data (kernel error) and on the FP64
+    data (storage error)."""
     from oracle import oracle as O
     lp = O.LP.from_instance(inst.rounded("f32"))
     t0 = time.perf_counter()
     n = 0
     while True:
-        O.dual_eval(lp, lam_np, gamma)
+        ev32 = O.dual_eval(lp, lam_np, gamma)
         n += 1
         el = time.perf_counter() - t0
         if el >= budget_s or n >= 3 or el * (n + 1) / n > budget_s * 1.5:
             break
     per = el / n
-    return {"value": 1.0 / per, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} full FP64 dual-gradient evaluation(s) of the same {inst.n}-nnz "
-                      f"instance on one host core ({per:.2f} s each); the O(m) ascent step is "
-                      f"not included"}
+    out = {"value": 1.0 / per, "unit": "iter/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n} full FP64 dual-gradient evaluation(s) of the same {inst.n}-nnz "
+                     f"instance on one host core ({per:.2f} s each); the O(m) ascent step is "
+                     f"not included"}
+    prec = None
+    if gpu_evals:
+        ev64 = O.dual_eval(O.LP.from_instance(inst), lam_np, gamma)
+
+        def errs(g, grad, ev, ref):
+            scale = np.bincount(inst.dst, weights=np.abs(ref.a * ev.x), minlength=inst.m) + \
+                np.abs(inst.b)
+            ge = np.abs(grad - ev.grad) / np.maximum(scale, 1e-300)
+            return abs(g - ev.g) / max(1.0, abs(ev.g)), float(ge.max())
+
+        prec = {"lambda": "final lambda of the timed FP32 solve", "gamma": gamma,
+                "tolerance": {"grad_componentwise": 1e-5, "g": 1e-6},
+                "oracle_g_fp64_data": ev64.g}
+        for st, (g, grad) in gpu_evals.items():
+            d = {}
+            if st == "f32":
+                # the timed oracle evaluations above ran on the FP32-rounded data
+                d["g_rel_err_same_data"], d["grad_max_rel_err_same_data"] = \
+                    errs(g, grad, ev32, inst.rounded("f32"))
+            d["g_rel_err_fp64_data"], d["grad_max_rel_err_fp64_data"] = errs(g, grad, ev64, inst)
+            prec[st] = d
+    return out, prec
 
 
 def load_or_generate(I, args):
@@ -236,6 +261,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16 / FP64 storage runs and the error statement")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the work layout by timing candidates on a sample at create")
     ap.add_argument("--cache", default=None,
@@ -297,6 +324,12 @@ def main():
         return lam, r, el
 
     lam, r, el = timed(prob)
+    # the other storage types at the same lambda (errors stated against the
+    # oracle in the CPU-baseline leg) and their iteration rate
+    gpu_evals = {}
+    if not args.no_precision:
+        g32, _, e32 = prob.dual_grad(lam, gamma, want_eval=True)
+        gpu_evals[args.storage] = (e32["g"], g32.cpu().numpy())
     ms = el * 1e3 / args.steps
     ips = args.steps / el
     bytes_per = info["stream_bytes"]
@@ -362,11 +395,35 @@ def main():
             "final_rel_gap": rb.rel_gap}
     lam_np = lam.cpu().numpy()
     prob.close()
+    storages = {}
+    if not args.no_precision:
+        for st in ("bf16", "f64"):
+            if st == args.storage:
+                continue
+            with Problem(inst, storage=st) as ps:
+                p_steps = max(1, min(args.steps, 300))
+                ps.solve(settings(min(args.warmup, 20)))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, rs = ps.solve(settings(p_steps))
+                torch.cuda.synchronize()
+                els = time.perf_counter() - t0
+                gs, _, es = ps.dual_grad(lam, gamma, want_eval=True)
+                gpu_evals[st] = (es["g"], gs.cpu().numpy())
+                sb = ps.info()["stream_bytes"]
+                storages[st] = {"iter_per_s": p_steps / els, "steps": p_steps,
+                                "grad_kernel_ms": rs.grad_kernel_ms,
+                                "achieved_gbs": sb / (rs.grad_kernel_ms * 1e-3) / 1e9,
+                                "bytes_per_launch": sb}
+        out["storage_variants"] = storages
     if args.systems:
         out.update(systems(args, log))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(inst, lam_np, gamma, args.cpu_budget)
+        out["cpu_baseline"], prec = cpu_baseline(inst, lam_np, gamma, args.cpu_budget,
+                                                 gpu_evals if gpu_evals else None)
+        if prec is not None:
+            out["precision"] = prec
     print(json.dumps(out), flush=True)
 
 
