@@ -273,29 +273,42 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
     SolveState* st = a.st;
     __shared__ double red[9 * kSW];
     __shared__ double v[9];
+    // thread 0 reads the state before the reductions, so its loads overlap them
+    double cur_gamma = 0.0, cur_eta = 0.0, cur_eta_cap = 0.0, cur_tm = 0.0;
+    int64_t cur_k = 0, cur_ks = 0;
+    int32_t cur_stage = 0;
+    if (threadIdx.x == 0) {
+        cur_gamma = st->gamma;
+        cur_eta = st->eta;
+        cur_eta_cap = st->eta_cap;
+        cur_tm = st->tm;
+        cur_k = st->k;
+        cur_ks = st->ks;
+        cur_stage = st->stage;
+    }
     reduce_scalars(a.obj_part, a.nchunks, a.blockpart, a.nblk, v, red);
     const SolveParams& P = a.prm;
     if (threadIdx.x == 0) {
-        const int64_t k = st->k;
-        const int64_t ks = st->ks;
-        const double gamma = st->gamma;
+        const int64_t k = cur_k;
+        const int64_t ks = cur_ks;
+        const double gamma = cur_gamma;
         const double reg = 0.5 * gamma * v[1];
         const double g = -v[0] + reg - v[3];
         const double obj = v[2] + reg;
-        double eta = st->eta;
+        double eta = cur_eta;
         if (P.adaptive) {
             if (ks > 0 && v[6] > 0.0) {
                 const double Lh = sqrt(v[5]) / sqrt(v[6]);
-                eta = (Lh > 0.0 && 1.0 / Lh < st->eta_cap) ? 1.0 / Lh : st->eta_cap;
+                eta = (Lh > 0.0 && 1.0 / Lh < cur_eta_cap) ? 1.0 / Lh : cur_eta_cap;
             }
         } else {
-            eta = st->eta_cap;
+            eta = cur_eta_cap;
         }
         double rel = NAN;
         st->g = g;
         st->obj = obj;
         st->gamma_eval = gamma;
-        st->stage_eval = st->stage;
+        st->stage_eval = cur_stage;
         st->gnorm = sqrt(v[4]);
         if (a.check) {
             const double Pv = obj + v[7];
@@ -310,7 +323,7 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
             row[1] = rel;
             row[2] = eta;
             row[3] = gamma;
-            row[4] = (double)st->stage;
+            row[4] = (double)cur_stage;
             row[5] = sqrt(v[4]);
         }
         double stop = 0.0, advance = 0.0, beta = 0.0;
@@ -319,14 +332,14 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
             st->done = 1;
             stop = 1.0;
         } else {
-            const int last = st->stage == P.n_stages - 1;
+            const int last = cur_stage == P.n_stages - 1;
             if (a.check && last && rel <= P.tol) {
                 st->converged = 1;
                 st->done = 1;
                 st->k = k + 1;
                 stop = 1.0;
             } else {
-                const double tm = st->tm;
+                const double tm = cur_tm;
                 const double tn = P.momentum ? 0.5 * (1.0 + sqrt(1.0 + 4.0 * tm * tm)) : 1.0;
                 beta = P.momentum ? (tm - 1.0) / tn : 0.0;
                 if (!last) {
@@ -336,11 +349,11 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
                 st->eta = eta;
                 if (advance != 0.0) {
                     const double gnew = P.gamma0 * pow(P.gamma_final / P.gamma0,
-                                                       (double)(st->stage + 1) / (double)(P.n_stages - 1));
+                                                       (double)(cur_stage + 1) / (double)(P.n_stages - 1));
                     st->eta = eta * gnew / gamma;
                     st->eta_cap = P.max_step * gnew / P.gamma0;
                     st->gamma = gnew;
-                    st->stage += 1;
+                    st->stage = cur_stage + 1;
                     st->tm = 1.0;
                     st->ks = 0;
                 } else {
