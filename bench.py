@@ -237,6 +237,47 @@ def systems(args, log):
     return out
 
 
+def ablations(args, log):
+    """Section 7's ablations on a binding matching LP (greedy-load capacities,
+    Appendix B): iterations and time to rel_gap 1e-4 at gamma = 1e-3 with and
+    without Jacobi row normalization, with gamma continuation (geometric, 5
+    stages from 1e-1) and with gamma fixed, and the paper's own schedule
+    (0.16 -> 0.01 halved every 25 iterations).  The step cap is the safe 1/L
+    in every run: gamma after normalization (|A'|^2 = 1), gamma / max_j
+    |A_j|^2 without it."""
+    import torch
+    from paper_2603_04621_amd import instances as I
+    from paper_2603_04621_amd.api import Problem, SolveSettings
+    inst = I.large(I=args.ablation_sources, J=max(2, args.ablation_sources // 500),
+                   capacity="greedy")
+    rn2 = float(np.bincount(inst.dst, weights=inst.a ** 2, minlength=inst.m).max())
+    runs = []
+    cases = [("jacobi+continuation", True, 1e-1, 1e-3, 5, 2000, 1e-3),
+             ("none+continuation", False, 1e-1, 1e-3, 5, 2000, 1e-3),
+             ("jacobi+fixed", True, 1e-3, 1e-3, 1, 0, 0.0),
+             ("none+fixed", False, 1e-3, 1e-3, 1, 0, 0.0),
+             ("jacobi+paper-schedule", True, 0.16, 0.01, 5, 25, 0.0)]
+    for name, rnorm, g0, g1, ns, siters, stol in cases:
+        scale = 1.0 if rnorm else 1.0 / rn2
+        s = SolveSettings(gamma0=g0, gamma_final=g1, n_stages=ns, stage_iters=siters,
+                          stage_tol=stol, tol_rel_gap=1e-4, max_iters=args.ablation_iters,
+                          check_every=10, max_step=g0 * scale, init_step=1e-2 * g0 * scale)
+        with Problem(inst, storage="f32", row_normalize=rnorm) as p:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = p.solve(s)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        runs.append({"case": name, "converged": bool(r.converged), "iterations": int(r.iters),
+                     "seconds": el, "final_gamma": r.gamma, "rel_gap": r.rel_gap, "g": r.g})
+        log(f"ablation {runs[-1]}")
+    return {"workload": "matching LP: I=%d sources, J=%d destinations, degree 1+Poisson(9), "
+                        "Zipf(1.1), greedy-load capacities, FP32, to rel_gap 1e-4 (cap %d "
+                        "iterations)" % (args.ablation_sources, max(2, args.ablation_sources // 500),
+                                         args.ablation_iters),
+            "nnz": inst.n, "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +302,10 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--ablations", action="store_true",
+                    help="also run the preconditioning / continuation ablations")
+    ap.add_argument("--ablation-sources", type=int, default=1_000_000)
+    ap.add_argument("--ablation-iters", type=int, default=20000)
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16 / FP64 storage runs and the error statement")
     ap.add_argument("--autotune", action="store_true",
@@ -418,6 +463,8 @@ def main():
         out["storage_variants"] = storages
     if args.systems:
         out.update(systems(args, log))
+    if args.ablations:
+        out["ablations"] = ablations(args, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"], prec = cpu_baseline(inst, lam_np, gamma, args.cpu_budget,

@@ -194,6 +194,7 @@ extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, con
     int64_t seg = o->graph_iters > 0 ? o->graph_iters : (o->check_every > 0 ? o->check_every : 16);
     if (o->check_every > 0 && seg % o->check_every != 0) seg = o->check_every;
     int64_t k = 0;
+    bool all_done = false;
     const int64_t nfull = N / seg;
     if (nfull > 0) {
         GraphHolder gh;
@@ -218,11 +219,17 @@ extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, con
             if ((gi & 3) == 3 || gi == nfull - 1) {
                 int nd = 0;
                 TRY(br.count_done(s, &nd), "poll");
-                if (nd == count) break;
+                if (nd == count) {
+                    all_done = true;
+                    break;
+                }
             }
         }
     }
-    for (; k < N; ++k) TRY(br.enqueue_iteration(dlh::is_check_iter(o, k) ? 1 : 0, s), "batch iteration");
+    // the remainder of max_iters that fills no whole graph (none once every
+    // problem has stopped)
+    for (; k < N && !all_done; ++k)
+        TRY(br.enqueue_iteration(dlh::is_check_iter(o, k) ? 1 : 0, s), "batch iteration");
     for (int q = 0; q < count; ++q) {
         dl_problem* p = ps[q];
         TRY(launch_solve_final(p->st, p->y, p->yp, p->orig, p->D, p->J, lambdas[q], s), "final kernel");

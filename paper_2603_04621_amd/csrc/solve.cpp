@@ -106,6 +106,7 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
             if (hst->done) break;
         }
     } else {
+        bool stop = false;
         const int64_t nfull = N / seg;
         if (nfull > 0) {
             TRY(hipStreamCreateWithFlags(&cl.cap, hipStreamNonBlocking), "capture stream");
@@ -124,7 +125,6 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
             TRY(hipGraphInstantiate(&cl.exec, cl.graph, nullptr, nullptr, 0), "instantiate graph");
             cl.events.resize(2, nullptr);
             for (auto& e : cl.events) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-            bool stop = false;
             for (int64_t gi = 0; gi < nfull && !stop; ++gi) {
                 TRY(hipGraphLaunch(cl.exec, s), "graph launch");
                 k += seg;
@@ -137,7 +137,9 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
                 }
             }
         }
-        for (; k < N; ++k)
+        // the remainder of max_iters that fills no whole graph (none once the
+        // device has stopped: those launches would only return at once)
+        for (; k < N && !stop; ++k)
             TRY(dlh::enqueue_iteration(p, prm, dlh::is_check_iter(o, k) ? 1 : 0, cl.trace, s, nullptr, nullptr),
                 "iteration");
     }

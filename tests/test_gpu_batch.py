@@ -77,3 +77,37 @@ def test_batch_matches_oracle_member(dev):
     assert np.max(np.abs(la - r_or.lam)) <= 1e-5 * max(1.0, np.max(np.abs(r_or.lam)))
     for p in probs:
         p.close()
+
+
+def test_early_stop_does_not_run_out_the_iteration_cap(dev):
+    """A solve that reaches its gap long before max_iters returns promptly:
+    once the device has stopped, no further iterations are enqueued (solo
+    and batched).  Regression test: the remainder used to be launched
+    eagerly, one no-op iteration at a time."""
+    import time
+    import torch
+    from paper_2603_04621_amd.api import Problem, SolveSettings, batch_solve
+    inst = I.large(I=20_000, J=100, capacity="greedy")
+
+    def settings(cap):
+        return SolveSettings(gamma0=1e-2, gamma_final=1e-2, tol_rel_gap=1e-4, max_iters=cap,
+                             check_every=10, max_step=1e-2, init_step=1e-4)
+
+    with Problem(inst) as p:
+        times = {}
+        for cap in (5_000, 300_000):
+            p.solve(settings(cap))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = p.solve(settings(cap))
+            times[cap] = time.perf_counter() - t0
+            assert r.converged and r.iters < 5_000
+        assert times[300_000] < times[5_000] + 0.25, times
+        btimes = {}
+        for cap in (5_000, 300_000):
+            batch_solve([p], settings(cap))
+            t0 = time.perf_counter()
+            _, rs = batch_solve([p], settings(cap))
+            btimes[cap] = time.perf_counter() - t0
+            assert rs[0].converged
+        assert btimes[300_000] < btimes[5_000] + 0.25, btimes
