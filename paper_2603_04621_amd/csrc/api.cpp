@@ -703,6 +703,13 @@ extern "C" dl_status dl_problem_destroy(dl_problem* p)
     return DL_OK;
 }
 
+namespace dlh {
+void destroy_idle(dl_problem* p)
+{
+    if (p) free_problem(p);
+}
+}  // namespace dlh
+
 extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info)
 {
     if (!p || !info) { set_error("NULL argument"); return DL_ERR_INVALID_ARG; }

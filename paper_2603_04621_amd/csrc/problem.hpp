@@ -65,6 +65,10 @@ dl::AgdArgs agd_args(const dl_problem* p, const dl::SolveParams& prm, int check,
 hipError_t enqueue_iteration(dl_problem* p, const dl::SolveParams& prm, int check, double* trace,
                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
+// frees a problem whose device work the caller has already waited for
+// (no device-wide synchronization, unlike dl_problem_destroy)
+void destroy_idle(dl_problem* p);
+
 dl_status check_solve_opts(const dl_solve_opts* o);
 dl::SolveParams make_params(const dl_solve_opts* o);
 bool is_check_iter(const dl_solve_opts* o, int64_t k);

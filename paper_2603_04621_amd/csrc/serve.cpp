@@ -1,10 +1,12 @@
 // Serving: continuous batching of LP solve requests (see include/dualip.h).
 //
-// Two threads per server, each with its own HIP stream (default priority):
-//   loader     takes queued requests first-come first-served when a slot is
-//              free and the request's device footprint fits the HBM budget,
-//              builds and uploads its problem and initializes its iteration
-//              state -- while the device keeps iterating the admitted ones;
+// Threads per server, each with its own HIP stream (default priority):
+//   loaders    (kLoaders of them) take queued requests first-come first-served
+//              when a slot is free and the request's device footprint fits the
+//              HBM budget, build and upload its problem and initialize its
+//              iteration state -- while the device keeps iterating the
+//              admitted ones (building a layout is host work of about 15 ms
+//              per million nonzeros, so one loader would cap admissions);
 //   scheduler  runs ticks of kTick iterations (gap test on the last) over all
 //              active requests with the batched fused launches, retires the
 //              finished ones (lambda copied to host, memory released) and
@@ -31,7 +33,8 @@ using dlh::set_error;
 
 namespace {
 
-constexpr int kTick = 10;   // iterations per tick; the gap is tested on the last
+constexpr int kTick = 10;     // iterations per tick; the gap is tested on the last
+constexpr int kLoaders = 4;   // concurrent problem builds
 
 struct Request {
     uint64_t ticket = 0;
@@ -76,7 +79,8 @@ struct dl_server {
     size_t used = 0;
     int slots_used = 0;
     uint64_t next_ticket = 1;
-    std::thread loader, scheduler;
+    std::vector<std::thread> loaders;
+    std::thread scheduler;
 
     double now() const
     {
@@ -210,6 +214,7 @@ static void scheduler_main(dl_server* S)
         for (Request* r : fin) {
             dl_solve_result& res = r->res;
             std::memset(&res, 0, sizeof res);
+            bool idle = false;   // this stream waited for all of the problem's work
             const size_t k = std::find(active.begin(), active.end(), r) - active.begin();
             if (e == hipSuccess) {
                 const SolveState& f = states[k];
@@ -220,6 +225,7 @@ static void scheduler_main(dl_server* S)
                     e2 = hipMemcpyAsync(r->lam_host.data(), r->lam_dev, r->lam_host.size() * sizeof(double),
                                         hipMemcpyDeviceToHost, s);
                 if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+                idle = e2 == hipSuccess;
                 res.converged = f.converged;
                 res.stage = f.stage_eval;
                 res.iters = f.k;
@@ -233,7 +239,9 @@ static void scheduler_main(dl_server* S)
             } else {
                 res.status = DL_ERR_DEVICE;
             }
-            dl_problem_destroy(r->prob);
+            // its work ran on this stream, which the copy above waited for
+            if (idle) dlh::destroy_idle(r->prob);
+            else dl_problem_destroy(r->prob);
             r->prob = nullptr;
             (void)hipFree(r->lam_dev);
             r->lam_dev = nullptr;
@@ -262,7 +270,7 @@ extern "C" dl_status dl_server_create(size_t hbm_budget_bytes, int32_t max_slots
     S->max_slots = max_slots;
     if (hipGetDevice(&S->device) != hipSuccess) { delete S; set_error("no HIP device"); return DL_ERR_DEVICE; }
     S->t0 = std::chrono::steady_clock::now();
-    S->loader = std::thread(loader_main, S);
+    for (int i = 0; i < kLoaders; ++i) S->loaders.emplace_back(loader_main, S);
     S->scheduler = std::thread(scheduler_main, S);
     *out = S;
     return DL_OK;
@@ -371,7 +379,7 @@ extern "C" dl_status dl_server_destroy(dl_server* S)
         S->queue.clear();
         S->cv.notify_all();
     }
-    S->loader.join();
+    for (auto& t : S->loaders) t.join();
     S->scheduler.join();
     for (auto& kv : S->all) {
         if (kv.second->prob) dl_problem_destroy(kv.second->prob);
