@@ -228,6 +228,9 @@ def systems(args, log):
         "solves_per_s": len(reqs) / t_srv,
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
+        # admission (queue + build) and on-device time of the served requests
+        "p50_admission_s": float(np.percentile([r[2][1] - r[2][0] for r in res], 50)),
+        "p50_on_device_s": float(np.percentile([r[2][2] - r[2][1] for r in res], 50)),
         "sequential_solves_per_s": len(reqs) / done_prev,
         "sequential_p50_latency_s": float(np.percentile(seq_lat, 50)),
         "sequential_p99_latency_s": float(np.percentile(seq_lat, 99)),

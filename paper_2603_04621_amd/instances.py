@@ -230,14 +230,14 @@ def greedy_capacity(dst, a, block_off, J, seed_key, eps: float = 1e-2) -> np.nda
     load l_j; then b_j = rho_j (l_j + eps) with rho_j ~ U[0.5, 1] drawn from
     their own stream.  Some constraints bind at the optimum, others stay slack.
     """
-    I = block_off.shape[0] - 1
     deg = np.diff(block_off)
     nz = deg > 0
-    src = np.repeat(np.arange(I), deg)
-    # index of the largest a in each block (first one on ties)
-    order = np.lexsort((-a, src))
-    first = block_off[:-1][nz]
-    best = order[first]
+    starts = block_off[:-1][nz]
+    # index of the largest a in each block (first one on ties): the first
+    # position at or after the block start that holds the block maximum
+    mx = np.maximum.reduceat(a, starts)
+    hits = np.flatnonzero(a == np.repeat(mx, deg[nz]))
+    best = hits[np.searchsorted(hits, starts)]
     load = np.bincount(dst[best], weights=a[best], minlength=J)
     rho = np.random.default_rng(seed_key).uniform(0.5, 1.0, size=J)
     return rho * (load + eps)
