@@ -460,6 +460,12 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
     p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
     const bool f64 = opts.storage == DL_F64, tail = p->K < m;
+    // check passes: without tail rows the c x and v^2 x^2 sums of the first
+    // Kc rows join lam and the a x sums in LDS; with tail rows lam is read
+    // from memory and the three sums of all K rows are in LDS
+    p->Kc = tail ? p->K
+                 : (int)std::max<int64_t>(0, std::min<int64_t>(p->K, ((int64_t)max_lds - 4 * kWaves * 8 -
+                                                                      (int64_t)p->K * 12) / 8));
     p->lane_cap = std::min(lc.lane_cap, lane_cap(f64, p->has_w != 0, tail));
     p->seg_rmax = std::min(lc.seg_rmax, seg_rmax(f64, p->has_w != 0, tail));
     p->chunk_mult = lc.chunk_mult;
@@ -559,7 +565,8 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         if (e != hipSuccess) { st = hip_fail(e, "upload"); free_problem(p); return st; }
         e = hipHostMalloc((void**)&p->st_host, 2 * sizeof(SolveState), hipHostMallocDefault);
         if (e != hipSuccess) { p->st_host = nullptr; st = hip_fail(e, "pinned state"); free_problem(p); return st; }
-        e = set_grad_attributes(std::max(grad_lds_bytes(p->K, false), grad_lds_bytes(p->K, true)));
+        e = set_grad_attributes(std::max(grad_lds_bytes(p->K, p->Kc, false, p->K < p->J),
+                                         grad_lds_bytes(p->K, p->Kc, true, p->K < p->J)));
         if (e != hipSuccess) { st = hip_fail(e, "kernel LDS attribute"); free_problem(p); return st; }
     }
 #undef ALLOC
@@ -757,6 +764,7 @@ GradArgs grad_args(const dl_problem* p, const double* lam, const double* gamma_p
     g.done = done;
     g.J = p->J;
     g.K = p->K;
+    g.Kc = p->Kc;
     g.nchunks = p->nchunks;
     g.part = p->part;
     g.tail = p->tail;
@@ -772,6 +780,7 @@ ReduceArgs reduce_args(const dl_problem* p, int check, int mode, const double* l
     r.part = p->part;
     r.nchunks = p->nchunks;
     r.K = p->K;
+    r.Kc = p->Kc;
     r.J = p->J;
     r.check = check;
     r.mode = mode;

@@ -82,7 +82,9 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
         int maxc = 0;
         for (int k : idx) {
             maxc = std::max(maxc, probs[k]->nchunks);
-            G.lds = std::max({G.lds, grad_lds_bytes(probs[k]->K, false), grad_lds_bytes(probs[k]->K, true)});
+            const bool tl = probs[k]->K < probs[k]->J;
+            G.lds = std::max({G.lds, grad_lds_bytes(probs[k]->K, probs[k]->Kc, false, tl),
+                              grad_lds_bytes(probs[k]->K, probs[k]->Kc, true, tl)});
         }
         for (int c = 0; c < maxc; ++c)
             for (int k : idx)

@@ -147,11 +147,12 @@ __device__ __forceinline__ void wg_sum_max(double& s, double& m, double* red)
 // lam of row j: from LDS for rows below K; rows beyond K come from a raw
 // buffer load whose offset is pushed out of range (returns 0, no memory
 // access) for LDS rows, so no per-edge branch or flat load is needed.  Check
-// passes keep the LDS for the three sums and read lam from global memory.
+// passes of problems with rows beyond K keep the LDS for the three sums and
+// read lam from global memory.
 template <bool CHECK, bool TAIL>
 __device__ __forceinline__ double get_lam(const Lds& s, const GradArgs& g, int j)
 {
-    if (CHECK) return ldo(g.lam, (uint32_t)j);
+    if (CHECK && TAIL) return ldo(g.lam, (uint32_t)j);
     if (!TAIL) return s.lam[j];
     const double l = s.lam[j < g.K ? j : g.K - 1];
     const uint32_t off = j >= g.K ? (uint32_t)j * 8u : 0xFFFFFFFFu;
@@ -170,14 +171,21 @@ __device__ __forceinline__ void gl_add(double* p, double v)
 }
 
 // per-destination sums: rows below K in LDS (f32), the rest in FP64 global
-// accumulators (a separate, rarely taken path so the main loop stays lean)
-template <bool CHECK>
-__device__ __forceinline__ void accum_lds(const Lds& s, int j, double ax, double cx, double q)
+// accumulators (a separate, rarely taken path so the main loop stays lean).
+// Check passes without tail rows keep the c x and v^2 x^2 sums of the first
+// Kc rows in LDS and add the others to the global accumulators.
+template <bool CHECK, bool TAIL>
+__device__ __forceinline__ void accum_lds(const Lds& s, const GradArgs& g, int j, double ax, double cx, double q)
 {
     lds_add(&s.hg[j], (float)ax);
     if (CHECK) {
-        lds_add(&s.hc[j], (float)cx);
-        lds_add(&s.hq[j], (float)q);
+        if (TAIL || j < g.Kc) {
+            lds_add(&s.hc[j], (float)cx);
+            lds_add(&s.hq[j], (float)q);
+        } else {
+            gl_add(&g.tail[g.J + j], cx);
+            gl_add(&g.tail[2 * (int64_t)g.J + j], q);
+        }
     }
 }
 template <bool CHECK>
@@ -193,7 +201,7 @@ template <bool CHECK, bool TAIL>
 __device__ __forceinline__ void accum(const Lds& s, const GradArgs& g, int j, double ax, double cx,
                                       double q)
 {
-    if (!TAIL || j < g.K) accum_lds<CHECK>(s, j, ax, cx, q);
+    if (!TAIL || j < g.K) accum_lds<CHECK, TAIL>(s, g, j, ax, cx, q);
     else accum_tail<CHECK>(g, j, ax, cx, q);
 }
 
@@ -624,7 +632,7 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
             ob.oq += q2;
             const double cx = CHECK ? (double)v.c[k] * x : 0.0;
             if (CHECK) ob.oc += cx;
-            if (!TAIL || v.j[k] < g.K) accum_lds<CHECK>(s, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
+            if (!TAIL || v.j[k] < g.K) accum_lds<CHECK, TAIL>(s, g, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
             else tail = true;
         }
     }
@@ -727,7 +735,7 @@ __device__ __forceinline__ Item item_at(const Item& mine, int r)
 
 // a run of groups of one class (S, P, projection) starting at batch entry r:
 // the next group's loads are in flight while the current group projects.
-// Ordinary passes (lam from LDS) issue them before the t phase; passes that
+// Passes that read lam from LDS issue them before the t phase; passes that
 // gather lam from memory issue the gathers first, then the prefetch, so that
 // waiting for the gathers (older in the in-order memory counter) never waits
 // for the prefetch as well.  Returns the first entry not processed.
@@ -738,7 +746,7 @@ __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int
     static_assert(P <= 16, "pipelined lane runs hold at most 16 rows per group");
     constexpr int LG = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : S == 16 ? 4 : S == 32 ? 5 : 6;
     static_assert((1 << LG) == S, "S is a power of two up to 64");
-    constexpr bool EARLY = !CHECK && !TAIL;
+    constexpr bool EARLY = !TAIL;   // lam from LDS
     SegGeo q = seg_geo<S>(item_at(mine, r));
     LaneRaw<VT, BOX, HASW, P> cur;
     lane_load<0, P, S>(g, q, cur);
@@ -992,7 +1000,7 @@ __device__ __forceinline__ int wg_class(int d) { return d <= 2 * kWG ? 2 : d <= 
 template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
 __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, const Lds& s, double gamma, Obj& ob)
 {
-    constexpr bool EARLY = !CHECK && !TAIL;
+    constexpr bool EARLY = !TAIL;   // lam from LDS
     Item it = g.items[i];
     int64_t base = uni64(it.base);
     int d = uni(it.d);
@@ -1098,8 +1106,11 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     s.red = (double*)smem;
     unsigned char* p = smem + 4 * kWaves * sizeof(double);
     const int K = g.K;
+    // rows of the c x and v^2 x^2 sums in LDS (check passes)
+    const int KC = CHECK ? (TAIL ? K : g.Kc) : 0;
+    constexpr bool LAM_LDS = !(CHECK && TAIL);
     s.lam = nullptr;
-    if (!CHECK) {
+    if (LAM_LDS) {
         s.lam = (double*)p;
         p += (size_t)K * sizeof(double);
     }
@@ -1108,14 +1119,14 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     s.hc = s.hq = nullptr;
     if (CHECK) {
         s.hc = (float*)p;
-        p += (size_t)K * sizeof(float);
+        p += (size_t)KC * sizeof(float);
         s.hq = (float*)p;
     }
     const double gamma = g.gamma_ptr ? *g.gamma_ptr : g.gamma_val;
     // LDS rows: lam (8 rows per thread in flight at once) and zeroed sums
     {
         int j = threadIdx.x;
-        if (!CHECK) {
+        if (LAM_LDS) {
             for (; j + 7 * kWG < K; j += 8 * kWG) {
                 double l[8];
 #pragma unroll
@@ -1125,13 +1136,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             }
             for (; j < K; j += kWG) s.lam[j] = g.lam[j];
         }
-        for (j = threadIdx.x; j < K; j += kWG) {
-            s.hg[j] = 0.0f;
-            if (CHECK) {
+        for (j = threadIdx.x; j < K; j += kWG) s.hg[j] = 0.0f;
+        if (CHECK)
+            for (j = threadIdx.x; j < KC; j += kWG) {
                 s.hc[j] = 0.0f;
                 s.hq[j] = 0.0f;
             }
-        }
     }
     __syncthreads();
 
@@ -1183,13 +1193,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     // flush: this chunk's row of partial sums, and its objective part
     const int64_t plane = (int64_t)g.nchunks * K;
     float* row = g.part + (int64_t)chunk * K;
-    for (int j = threadIdx.x; j < K; j += kWG) {
-        row[j] = s.hg[j];
-        if (CHECK) {
+    for (int j = threadIdx.x; j < K; j += kWG) row[j] = s.hg[j];
+    if (CHECK)
+        for (int j = threadIdx.x; j < KC; j += kWG) {
             row[plane + j] = s.hc[j];
             row[2 * plane + j] = s.hq[j];
         }
-    }
     ob.ot = wave_sum(ob.ot);
     ob.oq = wave_sum(ob.oq);
     ob.oc = wave_sum(ob.oc);
@@ -1231,7 +1240,7 @@ __global__ __launch_bounds__(kWG) void grad_kernel_batch(const GradArgs* __restr
 template <typename VT, bool CHECK, bool HASW, bool TAIL>
 static hipError_t launch_grad_t(const GradArgs& a, hipStream_t s)
 {
-    const size_t lds = grad_lds_bytes(a.K, CHECK);
+    const size_t lds = grad_lds_bytes(a.K, a.Kc, CHECK, TAIL);
     hipLaunchKernelGGL((grad_kernel<VT, CHECK, HASW, TAIL>), dim3(a.nchunks), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }

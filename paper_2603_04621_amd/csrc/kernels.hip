@@ -33,10 +33,12 @@ hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, s
     }
 }
 
-size_t grad_lds_bytes(int K, bool check)
+size_t grad_lds_bytes(int K, int Kc, bool check, bool tail)
 {
-    return 4 * kWaves * sizeof(double) + (size_t)K * (check ? 3 * sizeof(float)
-                                                            : sizeof(double) + sizeof(float));
+    const size_t base = 4 * kWaves * sizeof(double);
+    if (!check) return base + (size_t)K * (sizeof(double) + sizeof(float));
+    if (tail) return base + (size_t)K * 3 * sizeof(float);
+    return base + (size_t)K * (sizeof(double) + sizeof(float)) + (size_t)Kc * 2 * sizeof(float);
 }
 
 hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s)
@@ -77,6 +79,11 @@ __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk
         double ax = 0.0, cj = 0.0, qj = 0.0;
         if (j < r.K) {
             for (int i = 0; i < kRedSlices; ++i) ax += sh[0][i][l];
+        } else {
+            ax = r.tail[j];
+            r.tail[j] = 0.0;
+        }
+        if (j < r.Kc) {
             if (r.check) {
                 for (int i = 0; i < kRedSlices; ++i) {
                     cj += sh[1][i][l];
@@ -84,8 +91,6 @@ __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk
                 }
             }
         } else {
-            ax = r.tail[j];
-            r.tail[j] = 0.0;
             cj = r.tail[r.J + j];
             qj = r.tail[2 * (int64_t)r.J + j];
             r.tail[r.J + j] = 0.0;
@@ -131,7 +136,7 @@ __device__ __forceinline__ void reduce_rows(const ReduceArgs& r, const int blk)
     const int64_t plane = (int64_t)r.nchunks * r.K;
     for (int p = 0; p < planes; ++p) {
         double acc = 0.0;
-        if (j < r.K) {
+        if (j < (p == 0 ? r.K : r.Kc)) {
             const int c0 = (int)(((int64_t)r.nchunks * q) / kRedSlices);
             const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / kRedSlices);
             const float* col = r.part + p * plane + j;

@@ -25,7 +25,8 @@ struct GradArgs {
     double gamma_val;
     const int32_t* done;     // early-exit flag or null
     int32_t J, K;            // rows; rows kept in LDS
-    int32_t nchunks, pad;
+    int32_t nchunks;
+    int32_t Kc;              // check passes: rows whose c x and v^2 x^2 sums stay in LDS
     float* part;             // [planes][nchunks][K]
     double* tail;            // [3][J] FP64 accumulators of rows >= K
     double* obj_part;        // [nchunks][3]: sum t x, sum v^2 x^2, sum c x (check)
@@ -35,7 +36,7 @@ struct GradArgs {
 struct ReduceArgs {
     const float* part;
     int32_t nchunks, K, J, check, mode;   // mode 0: solve (lam' space), 1: evaluation
-    int32_t pad;
+    int32_t Kc;              // rows whose c x and v^2 x^2 partials are in `part`
     double* tail;
     const double* b;         // [J] internal order
     const double* D;         // [J] row scale
@@ -68,7 +69,11 @@ struct AgdArgs {
     double* trace;           // [max_iters][6] or null
 };
 
-size_t grad_lds_bytes(int K, bool check);
+// dynamic LDS of a gradient launch.  Ordinary passes: lam (FP64) and the
+// a x sums of K rows.  Check passes of problems without tail rows: the same
+// plus the c x and v^2 x^2 sums of Kc rows; with tail rows (lam read from
+// memory): the three sums of K rows.
+size_t grad_lds_bytes(int K, int Kc, bool check, bool tail);
 
 // storage: 0 f64, 1 f32, 2 bf16 (a, c)
 hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s);

@@ -15,6 +15,7 @@ struct dl_problem {
     int storage = 1;
     int has_box = 0, has_w = 0, solve_ok = 1;
     int J = 0, K = 0;                  // rows; rows resident in LDS
+    int Kc = 0;                        // rows of the check-pass c x, v^2 x^2 sums in LDS
     int nchunks = 0, nitems = 0, nblk2 = 0;
     int64_t n_lane = 0, n_seg = 0, n_wg = 0;
     int lane_cap = 0, seg_rmax = 0, chunk_mult = 1, tuned = 0;   // work layout

@@ -149,6 +149,17 @@ def test_grad_zipf_large_degree_config_shape(O, dev):
     compare(O, inst, "f32", lam_for(inst, 3, 2.0), 1e-3)
 
 
+def test_grad_check_sums_partly_in_lds(O, dev):
+    """J = 10k destinations, all in LDS: the gap-check pass keeps lam and the
+    a x sums of every row in LDS but the c x and v^2 x^2 sums of only the
+    first rows (the rest through global accumulators)."""
+    inst = I.large(I=150_000, J=10_000, capacity="greedy")
+    with gpu_problem(inst) as p:
+        assert p.info()["lds_rows"] == inst.m
+    compare(O, inst, "f32", lam_for(inst, 15, 2.0), 1e-3)
+    compare(O, inst, "f64", lam_for(inst, 16, 2.0), 1e-2, grad_tol=1e-5)
+
+
 def test_grad_heavy_tailed_mixed(O, dev):
     inst = I.heavy(I=20_000, J=4_000, dmax=4096, capacity="greedy")
     compare(O, inst, "f32", lam_for(inst, 4, 2.0), 1e-2)
