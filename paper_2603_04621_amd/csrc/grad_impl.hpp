@@ -141,6 +141,28 @@ __device__ __forceinline__ void wg_sum_max(double& s, double& m, double* red)
     }
 }
 
+// a sum and the two largest values over the whole workgroup
+__device__ __forceinline__ void wg_sum_top2(double& s, double& m1, double& m2, double* red)
+{
+    s = wave_sum(s);
+    wave_top2(m1, m2);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = s;
+        red[kWaves + w] = m1;
+        red[2 * kWaves + w] = m2;
+    }
+    __syncthreads();
+    s = 0.0;
+    m1 = -INFINITY;
+    m2 = -INFINITY;
+    for (int i = 0; i < kWaves; ++i) {
+        s += red[i];
+        top2_merge(m1, m2, red[kWaves + i], red[2 * kWaves + i]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-edge helpers
 // ---------------------------------------------------------------------------
@@ -317,6 +339,11 @@ __device__ __forceinline__ double seg_max(double v)
     return grp_max<S>(v);
 }
 template <int S>
+__device__ __forceinline__ void seg_top2(double& m1, double& m2)
+{
+    grp_top2<S>(m1, m2);
+}
+template <int S>
 __device__ __forceinline__ int seg_sum_i(int v)
 {
     return grp_sum_i<S>(v);
@@ -415,17 +442,20 @@ __device__ __forceinline__ double seg_threshold(const double (&t)[P], const floa
 {
     double tau = 0.0;
     if (!HASW) {
-        double sp = 0.0, mt = -INFINITY;
+        double sp = 0.0, mt = -INFINITY, m2 = -INFINITY;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             sp += t[k] > 0.0 ? t[k] : 0.0;
-            mt = t[k] > mt ? t[k] : mt;
+            m2 = fmax(m2, fmin(mt, t[k]));
+            mt = fmax(mt, t[k]);
         }
         sp = seg_sum<S>(sp);
-        mt = seg_max<S>(mt);
+        seg_top2<S>(mt, m2);
         bool live = sp > gamma;
         if (!__builtin_amdgcn_ballot_w64(live)) return 0.0;
         double tv = live ? (mt - gamma > 0.0 ? mt - gamma : 0.0) : 0.0;
+        // segments with one t above tau_0 are done (see the one-lane case)
+        if (!__builtin_amdgcn_ballot_w64(live && m2 > tv)) return tv;
         double st = 0.0;
         int n = 0;
 #pragma unroll
@@ -539,14 +569,18 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
     } else if (!BOX && !HASW) {
         // uniform weight w = 1/gamma: sum max(0, w t) > 1  <=>  sum max(0, t) > gamma,
         // tau_0 = max(0, max t - gamma), tau <- (sum_S t - gamma) / |S|
-        double sp = 0.0, mt = -INFINITY;
+        // m2: second largest t.  With m2 <= tau_0 only the largest t is above
+        // tau_0, so tau_0 = max t - gamma is the threshold (the iteration would
+        // return it unchanged); otherwise iterate.
+        double sp = 0.0, mt = -INFINITY, m2 = -INFINITY;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             sp += t[k] > 0.0 ? t[k] : 0.0;
-            mt = t[k] > mt ? t[k] : mt;
+            m2 = fmax(m2, fmin(mt, t[k]));
+            mt = fmax(mt, t[k]);
         }
-        if (sp > gamma) {
-            tau = mt - gamma > 0.0 ? mt - gamma : 0.0;
+        if (sp > gamma) tau = mt - gamma > 0.0 ? mt - gamma : 0.0;
+        if (sp > gamma && m2 > tau) {
             double st = 0.0;
             int n = 0;
 #pragma unroll
@@ -932,17 +966,29 @@ __device__ __forceinline__ void wg_project(const GradArgs& g, const Lds& s, cons
     const double* t = v.t;
     double tau = 0.0;
     if (!BOX) {
-        double s0 = 0.0, mx = -INFINITY;
+        // uniform weights: the two largest t; with the second at most tau_0 =
+        // max t - 1/w only the largest is active and tau_0 is the threshold
+        double s0 = 0.0, mx = -INFINITY, m2 = -INFINITY;
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
             const double w = HASW ? (double)v.w[k] * inv_g : inv_g;
             const double z = w * t[k];
             s0 += z > 0.0 ? z : 0.0;
-            mx = fmax(mx, t[k] - 1.0 / w);
+            if (HASW) {
+                mx = fmax(mx, t[k] - 1.0 / w);
+            } else {
+                m2 = fmax(m2, fmin(mx, t[k]));
+                mx = fmax(mx, t[k]);
+            }
         }
-        wg_sum_max(s0, mx, s.red);
-        if (s0 > 1.0) {
-            tau = mx > 0.0 ? mx : 0.0;
+        if (HASW) {
+            wg_sum_max(s0, mx, s.red);
+        } else {
+            wg_sum_top2(s0, mx, m2, s.red);
+            mx = mx - 1.0 / inv_g;
+        }
+        if (s0 > 1.0) tau = mx > 0.0 ? mx : 0.0;
+        if (s0 > 1.0 && (HASW || m2 > tau)) {
             double sw = 0.0, swt = 0.0;
             int n = 0;
 #pragma unroll

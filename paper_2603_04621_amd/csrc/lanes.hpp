@@ -70,6 +70,44 @@ __device__ __forceinline__ double grp_max(double v)
     }
     return v;
 }
+// largest and second largest value (with multiplicity) over aligned groups of
+// S lanes; every lane enters its own top two (m1 >= m2)
+__device__ __forceinline__ void top2_merge(double& m1, double& m2, const double p1, const double p2)
+{
+    m2 = fmax(fmin(m1, p1), fmax(m2, p2));
+    m1 = fmax(m1, p1);
+}
+template <int CTRL>
+__device__ __forceinline__ void top2_step(double& m1, double& m2)
+{
+    const double p1 = dpp64<CTRL>(m1), p2 = dpp64<CTRL>(m2);
+    top2_merge(m1, m2, p1, p2);
+}
+template <int S>
+__device__ __forceinline__ void grp_top2(double& m1, double& m2)
+{
+    if (S >= 2) top2_step<kDppXor1>(m1, m2);
+    if (S >= 4) top2_step<kDppXor2>(m1, m2);
+    if (S >= 8) top2_step<kDppHalfMirror>(m1, m2);
+    if (S >= 16) top2_step<kDppMirror>(m1, m2);
+    if (S >= 32) {
+        double a1 = rdlane64(m1, 0), a2 = rdlane64(m2, 0);
+        double b1 = rdlane64(m1, 16), b2 = rdlane64(m2, 16);
+        top2_merge(a1, a2, b1, b2);
+        double c1 = rdlane64(m1, 32), c2 = rdlane64(m2, 32);
+        const double d1 = rdlane64(m1, 48), d2 = rdlane64(m2, 48);
+        top2_merge(c1, c2, d1, d2);
+        if (S == 64) {
+            top2_merge(a1, a2, c1, c2);
+            m1 = a1;
+            m2 = a2;
+        } else {
+            const bool hi = (threadIdx.x & 32) != 0;
+            m1 = hi ? c1 : a1;
+            m2 = hi ? c2 : a2;
+        }
+    }
+}
 template <int S>
 __device__ __forceinline__ int grp_sum_i(int v)
 {
@@ -89,6 +127,7 @@ __device__ __forceinline__ int grp_sum_i(int v)
 }
 __device__ __forceinline__ double wave_sum(double v) { return grp_sum<64>(v); }
 __device__ __forceinline__ double wave_max(double v) { return grp_max<64>(v); }
+__device__ __forceinline__ void wave_top2(double& m1, double& m2) { grp_top2<64>(m1, m2); }
 __device__ __forceinline__ int wave_sum_i(int v) { return grp_sum_i<64>(v); }
 
 }  // namespace dl
