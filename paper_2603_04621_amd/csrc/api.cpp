@@ -236,9 +236,10 @@ static int block_lg(int64_t d, int cap, int rmax)
 // Groups blocks by (lanes per block, projection, degree), deals the work
 // items of each kind round-robin to the chunks (in that order, so every
 // chunk gets the same mix of sizes and the same share of nonzeros: a chunk's
-// time follows its number of items as much as its nonzeros) and lays the
-// stream out chunk by chunk, so each workgroup reads one contiguous region
-// per kind.
+// time follows its number of items as much as its nonzeros; WG blocks, few
+// and of very different sizes, go in decreasing size with the direction of
+// the deal reversed every round) and lays the stream out chunk by chunk, so
+// each workgroup reads one contiguous region per kind.
 static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, HostLayout& L)
 {
     const int64_t I = d->num_blocks;
@@ -257,7 +258,13 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
         if (lg >= 0) bucket(lg, pr, deg).push_back(i);
         else wgb.push_back({(int64_t)pr, i});
     }
-    std::stable_sort(wgb.begin(), wgb.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    // WG blocks by projection, then by decreasing degree (dealt below in a
+    // serpentine so every chunk gets the same share of their nonzeros)
+    auto bdeg = [&](int64_t i) { return d->block_off[i + 1] - d->block_off[i]; };
+    std::stable_sort(wgb.begin(), wgb.end(), [&](auto& a, auto& b) {
+        if (a.first != b.first) return a.first < b.first;
+        return bdeg(a.second) > bdeg(b.second);
+    });
 
     // items of each kind in order; gb holds their blocks
     struct Proto {
@@ -292,8 +299,9 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
     }
     L.n_wg = (int64_t)kinds[1].size();
 
-    // deal: chunk c takes items c, c + nchunks, ... of each kind; stream
-    // positions follow the final item order
+    // deal: chunk c takes items c, c + nchunks, ... of each kind (WG items:
+    // item r nchunks + c in even rounds r, r nchunks + nchunks - 1 - c in odd
+    // ones); stream positions follow the final item order
     L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0});
     std::vector<int64_t> g0s;
     int64_t pos = 0;
@@ -302,7 +310,10 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
         for (int c = 0; c < nchunks; ++c) {
             int32_t* r = k == 0 ? &L.chunks[c].a0 : &L.chunks[c].b0;
             r[0] = (int32_t)L.items.size();
-            for (size_t q = (size_t)c; q < v.size(); q += (size_t)nchunks) {
+            for (size_t r0 = 0; r0 < v.size(); r0 += (size_t)nchunks) {
+                const bool back = k == 1 && (r0 / (size_t)nchunks) % 2 == 1;
+                const size_t q = r0 + (back ? (size_t)(nchunks - 1 - c) : (size_t)c);
+                if (q >= v.size()) continue;
                 Item it = v[q].it;
                 it.base = pos;
                 pos += (int64_t)it.d * it.nb;
