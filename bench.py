@@ -98,6 +98,30 @@ def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0, gpu_evals=None):
     return out, prec
 
 
+def cpu_parallel_baseline(inst, lam_np, gamma, evals: int = 3):
+    """The same dual-gradient evaluation on all host cores (OpenMP C, FP64 on
+    the FP32-rounded data; not the oracle): mean of `evals` whole-instance
+    evaluations after one warm-up."""
+    from oracle import cpu_parallel as CP
+    arr = CP.Arrays(inst.rounded("f32"))
+    CP.dual_grad(arr, lam_np, gamma)
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        _, _, nt = CP.dual_grad(arr, lam_np, gamma)
+    per = (time.perf_counter() - t0) / evals
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": 1.0 / per, "unit": "iter/s", "cores": nt, "kind": "openmp",
+            "nproc": os.cpu_count(), "cpu_model": model,
+            "sample": f"{evals} full FP64 dual-gradient evaluations of the same {inst.n}-nnz "
+                      f"instance on {nt} threads ({per * 1e3:.1f} ms each); the O(m) ascent "
+                      f"step is not included"}
+
+
 def load_or_generate(I, args):
     fields = ("dst", "a", "c", "b", "block_off", "block_proj", "upper")
     tag = f"{args.config}_{args.sources}_{args.dests}"
@@ -121,6 +145,53 @@ def load_or_generate(I, args):
             if getattr(inst, f) is not None:
                 np.save(os.path.join(d, f + ".npy"), getattr(inst, f))
     return inst
+
+
+def serve_stream_run(reqs, arrivals, st, slots):
+    """Submits reqs[k] at arrivals[k] seconds to a fresh server; returns the
+    wall time from the first arrival to the last completion, per-request
+    latencies (completion - arrival) and the poll results."""
+    srv = Server(hbm_budget_bytes=200e9, max_slots=slots)
+    tickets = [None] * len(reqs)
+    t_arr = [None] * len(reqs)
+    start = time.perf_counter()
+
+    def feeder():
+        for k, ta in enumerate(arrivals):
+            dt = start + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            t_arr[k] = time.perf_counter()
+            tickets[k] = srv.submit(reqs[k], st)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    lat, res = [None] * len(reqs), [None] * len(reqs)
+    left = set(range(len(reqs)))
+    while left:
+        for k in list(left):
+            if tickets[k] is None:
+                continue
+            o = srv.poll(tickets[k])
+            if o is not None:
+                res[k] = o
+                lat[k] = time.perf_counter() - t_arr[k]
+                left.discard(k)
+        time.sleep(0.0005)
+    th.join()
+    t_srv = time.perf_counter() - start
+    srv.close()
+    return t_srv, np.array(lat), res
+
+
+def fcfs_latencies(arrivals, service):
+    """Latencies of one-at-a-time service in arrival order."""
+    done_prev, out = 0.0, []
+    for ta, sv in zip(arrivals, service):
+        begin = max(ta, done_prev)
+        done_prev = begin + sv
+        out.append(done_prev - ta)
+    return np.array(out), done_prev
 
 
 def systems(args, log):
@@ -173,36 +244,7 @@ def systems(args, log):
     reqs = [I.serve_member(n, k, capacity="greedy") for k, (_, n) in enumerate(arr)]
     log(f"serve: {len(reqs)} requests, {sum(x.n for x in reqs)} nnz generated in "
         f"{time.perf_counter() - t0:.1f}s")
-    srv = Server(hbm_budget_bytes=200e9, max_slots=args.serve_slots)
-    tickets = [None] * len(reqs)
-    t_arr = [None] * len(reqs)
-    start = time.perf_counter()
-
-    def feeder():
-        for k, (ta, _) in enumerate(arr):
-            dt = start + ta - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            t_arr[k] = time.perf_counter()
-            tickets[k] = srv.submit(reqs[k], st)
-
-    th = threading.Thread(target=feeder)
-    th.start()
-    lat, res = [None] * len(reqs), [None] * len(reqs)
-    left = set(range(len(reqs)))
-    while left:
-        for k in list(left):
-            if tickets[k] is None:
-                continue
-            o = srv.poll(tickets[k])
-            if o is not None:
-                res[k] = o
-                lat[k] = time.perf_counter() - t_arr[k]
-                left.discard(k)
-        time.sleep(0.0005)
-    th.join()
-    t_srv = time.perf_counter() - start
-    srv.close()
+    t_srv, lat, res = serve_stream_run(reqs, [ta for ta, _ in arr], st, args.serve_slots)
     # one-at-a-time baseline: measured create + solve per request, first come
     # first served on the same arrival times
     svc = []
@@ -213,13 +255,7 @@ def systems(args, log):
             p.solve(st)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t1)
-    done_prev, seq_lat = 0.0, []
-    for (ta, _), sv in zip(arr, svc):
-        begin = max(ta, done_prev)
-        done_prev = begin + sv
-        seq_lat.append(done_prev - ta)
-    lat = np.array(lat)
-    seq_lat = np.array(seq_lat)
+    seq_lat, done_prev = fcfs_latencies([ta for ta, _ in arr], svc)
     out["served"] = {
         "workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate:g}/s, "
                     f"I log-uniform [1e4, {args.serve_hi:.0e}], J = I/500, 70/30 simplex/box, "
@@ -237,6 +273,22 @@ def systems(args, log):
         "converged": int(sum(r[0].converged for r in res)),
     }
     log(f"served: {out['served']}")
+    # below saturation: the same requests with their arrival times stretched
+    # to lower rates
+    sweep = []
+    for rate in [float(x) for x in args.serve_sweep.split(",") if x]:
+        arr_r = [ta * args.serve_rate / rate for ta, _ in arr]
+        t_r, lat_r, res_r = serve_stream_run(reqs, arr_r, st, args.serve_slots)
+        sl, sd = fcfs_latencies(arr_r, svc)
+        sweep.append({"rate": rate, "solves_per_s": len(reqs) / t_r,
+                      "p50_latency_s": float(np.percentile(lat_r, 50)),
+                      "p99_latency_s": float(np.percentile(lat_r, 99)),
+                      "sequential_solves_per_s": len(reqs) / sd,
+                      "sequential_p50_latency_s": float(np.percentile(sl, 50)),
+                      "sequential_p99_latency_s": float(np.percentile(sl, 99)),
+                      "converged": int(sum(r[0].converged for r in res_r))})
+        log(f"served at {rate:g}/s: {sweep[-1]}")
+    out["served"]["rate_sweep"] = sweep
     return out
 
 
@@ -303,6 +355,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-hi", type=float, default=5e5)
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-sweep", default="25,50,100",
+                    help="lower arrival rates (req/s) re-run with the same requests; empty: none")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--ablations", action="store_true",
@@ -474,6 +528,8 @@ def main():
                                                  gpu_evals if gpu_evals else None)
         if prec is not None:
             out["precision"] = prec
+        log("timing the multi-core CPU baseline")
+        out["cpu_parallel_baseline"] = cpu_parallel_baseline(inst, lam_np, gamma)
     print(json.dumps(out), flush=True)
 
 
