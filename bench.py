@@ -151,6 +151,8 @@ def serve_stream_run(reqs, arrivals, st, slots):
     """Submits reqs[k] at arrivals[k] seconds to a fresh server; returns the
     wall time from the first arrival to the last completion, per-request
     latencies (completion - arrival) and the poll results."""
+    import threading
+    from paper_2603_04621_amd.api import Server
     srv = Server(hbm_budget_bytes=200e9, max_slots=slots)
     tickets = [None] * len(reqs)
     t_arr = [None] * len(reqs)
