@@ -242,6 +242,54 @@ def test_edge_cases(O, dev):
         compare(O, big, "f64", lam, 1e-2, grad_tol=1e-5)
 
 
+def tie_instance(gamma, seed=11):
+    """Blocks of every item kind (lam = 0, a = 1, so t = -c) with the largest
+    t = 3/4 and the second 3/4 (a tie), 3/4 - gamma/2 or 3/4 - 3 gamma/2; the
+    other t lie in [1/4, 1/2].  With gamma = 1/64 every value sits on a grid
+    that bf16, f32 and f64 store exactly."""
+    rng = np.random.default_rng(seed)
+    J = 2500
+    degs, cs = [], []
+    for d in (2, 3, 10, 30, 40, 100, 500, 2000):
+        for case in ("tie", "near", "gap", "gap") * 3:
+            c = -np.round(rng.uniform(0.25, 0.5, size=d) * 64) / 64
+            top, second = rng.choice(d, size=2, replace=False)
+            c[top] = -0.75
+            c[second] = -0.75 + {"tie": 0.0, "near": 0.5 * gamma, "gap": 1.5 * gamma}[case]
+            degs.append(d)
+            cs.append(c)
+    deg = np.array(degs, dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    n = int(off[-1])
+    dst = np.concatenate([rng.choice(J, size=d, replace=False) for d in deg]).astype(np.int32)
+    a = np.ones(n)
+    c = np.concatenate(cs)
+    b = 0.3 * np.bincount(dst, weights=a, minlength=J)
+    return I.Instance(J, n, dst, a, c, b, off, np.zeros(deg.size, dtype=np.uint8), None,
+                      "ties", seed)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_grad_ties_and_near_ties(O, dev, storage):
+    # the simplex threshold skips its fixed-point passes only when the second
+    # largest t is at most max t - gamma; exact ties and near ties must take
+    # the full passes and still match the oracle (gamma on the value grid)
+    gamma = 1.0 / 64
+    inst = tie_instance(gamma)
+    compare(O, inst, storage, np.zeros(inst.m), gamma)
+    with gpu_problem(inst, storage) as p:
+        _, x, _ = p.dual_grad(torch.zeros(inst.m, dtype=torch.float64), gamma, want_x=True)
+        x = x.cpu().numpy()
+    for i in range(inst.block_off.shape[0] - 1):
+        xb = x[inst.block_off[i]:inst.block_off[i + 1]]
+        k = i % 4
+        pos = int(np.sum(xb > 0))
+        # tie: two edges at 1/2 each; near: two edges (3/4, 1/4); gap: one edge at 1
+        assert pos == (1 if k == 2 or k == 3 else 2), (i, pos)
+        assert abs(xb.sum() - 1.0) < 1e-9
+    compare(O, inst, storage, lam_for(inst, 3, 0.01), gamma)
+
+
 def test_grad_repeatable(dev):
     """Repeated evaluations differ only by the order of the f32 LDS atomic
     adds: far inside the gradient tolerance; g (which does not use those sums)
