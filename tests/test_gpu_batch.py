@@ -59,6 +59,28 @@ def test_batch_equals_solo(dev, storage):
         p.close()
 
 
+def test_batch_mixed_kernel_groups(dev):
+    """One batch whose members need different gradient kernels (FP32, BF16,
+    per-edge primal scales, rows beyond LDS, box blocks): each member's
+    batched solve equals its solo solve."""
+    from paper_2603_04621_amd.api import Problem, SolveSettings, batch_solve
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=3, stage_iters=300, stage_tol=1e-3,
+                      tol_rel_gap=1e-4, max_iters=1200, check_every=10, max_step=1e-1,
+                      init_step=1e-3)
+    small = make_batch(count=3, seed=4621300)
+    rows_beyond_lds = I.heavy(I=30_000, J=16_000, dmax=300, capacity="greedy")
+    members = [(small[0], "f32", 0), (small[1], "bf16", 0), (small[2], "f32", 1),
+               (small[3], "bf16", 0), (rows_beyond_lds, "f32", 0)]
+    probs = [Problem(x, storage=st, primal_scale=ps) for x, st, ps in members]
+    assert probs[-1].info()["lds_rows"] < rows_beyond_lds.m
+    solo = [p.solve(s) for p in probs]
+    lams, outs = batch_solve(probs, s)
+    for k, ((l1, r1), l2, r2) in enumerate(zip(solo, lams, outs)):
+        same_solve(k, l1.cpu().numpy(), r1, l2.cpu().numpy(), r2, s)
+    for p in probs:
+        p.close()
+
+
 def test_batch_matches_oracle_member(dev):
     """One batched member against the CPU oracle directly (FP64 storage)."""
     from oracle import oracle as O
