@@ -18,7 +18,9 @@
 // hold for the final set), not limited by a bisection tolerance.  Because
 // tau_1 > tau_0 (the top edge alone already gives w (t - tau_0) = 1) every
 // set along the way is a threshold set {t > tau}, so no membership mask is
-// kept.
+// kept.  With uniform weights the first pass also finds the second-largest
+// t; when it is at most tau_0 only the largest t is active, tau_0 is already
+// the threshold and the fixed-point passes are skipped.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
