@@ -26,31 +26,50 @@ void BatchRunner::release()
     f(ndone_dev_);
     f(st_dev_);
     if (ndone_host_) (void)hipHostFree(ndone_host_);
+    if (st_host_) (void)hipHostFree(st_host_);
     gtab_ = nullptr;
     rtab_[0] = rtab_[1] = nullptr;
     atab_[0] = atab_[1] = nullptr;
     ctab_ = rbt_ = nullptr;
     ndone_dev_ = ndone_host_ = nullptr;
     st_dev_ = nullptr;
+    st_host_ = nullptr;
     st_cap_ = 0;
+    for (size_t& c : cap_) c = 0;
     probs_.clear();
     groups_.clear();
 }
 
+// copies v into *dst, growing the allocation (by half again) only when it is
+// too small: the server rebuilds its tables at every admission and
+// retirement, and allocation calls cost more than the copies
 template <typename T>
-static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
+static hipError_t upload(T** dst, size_t* cap, const std::vector<T>& v, hipStream_t s)
 {
-    hipError_t e = hipMalloc((void**)dst, std::max<size_t>(1, v.size()) * sizeof(T));
-    if (e != hipSuccess) return e;
-    if (!v.empty()) e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-    return e;
+    const size_t need = std::max<size_t>(1, v.size());
+    if (*cap < need) {
+        if (*dst) (void)hipFree(*dst);
+        *dst = nullptr;
+        *cap = 0;
+        const size_t want = need + need / 2;
+        hipError_t e = hipMalloc((void**)dst, want * sizeof(T));
+        if (e != hipSuccess) {
+            *dst = nullptr;
+            return e;
+        }
+        *cap = want;
+    }
+    if (!v.empty()) return hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return hipSuccess;
 }
 
 dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::vector<SolveParams>& prm,
                              hipStream_t s)
 {
-    release();
+    // the stream has no work of the previous tables in flight (callers build
+    // between synchronized ticks), so their allocations are reused
     probs_ = probs;
+    groups_.clear();
     const int n = (int)probs.size();
     std::vector<GradArgs> g(n);
     std::vector<ReduceArgs> r0(n), r1(n);
@@ -96,21 +115,38 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
         for (int b = 0; b < probs[k]->nblk2; ++b) rb.push_back(make_int2(k, b));
     nrb_ = (int)rb.size();
     hipError_t e;
-    if ((e = upload(&gtab_, g, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = upload(&rtab_[0], r0, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = upload(&rtab_[1], r1, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = upload(&atab_[0], a0, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = upload(&atab_[1], a1, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = upload(&ctab_, ct, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = upload(&rbt_, rb, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = hipMalloc((void**)&ndone_dev_, sizeof(int))) != hipSuccess) return hip_fail(e, "batch flag");
-    if ((e = hipHostMalloc((void**)&ndone_host_, sizeof(int), hipHostMallocDefault)) != hipSuccess) {
+    if ((e = upload(&gtab_, &cap_[0], g, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&rtab_[0], &cap_[1], r0, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&rtab_[1], &cap_[2], r1, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&atab_[0], &cap_[3], a0, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&atab_[1], &cap_[4], a1, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&ctab_, &cap_[5], ct, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = upload(&rbt_, &cap_[6], rb, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if (!ndone_dev_ && (e = hipMalloc((void**)&ndone_dev_, sizeof(int))) != hipSuccess) {
+        ndone_dev_ = nullptr;
+        return hip_fail(e, "batch flag");
+    }
+    if (!ndone_host_ && (e = hipHostMalloc((void**)&ndone_host_, sizeof(int), hipHostMallocDefault)) != hipSuccess) {
         ndone_host_ = nullptr;
         return hip_fail(e, "batch flag");
     }
-    if ((e = hipMalloc((void**)&st_dev_, std::max(1, n) * sizeof(SolveState))) != hipSuccess)
-        return hip_fail(e, "batch states");
-    st_cap_ = (size_t)n;
+    if (st_cap_ < (size_t)std::max(1, n)) {
+        if (st_dev_) (void)hipFree(st_dev_);
+        if (st_host_) (void)hipHostFree(st_host_);
+        st_dev_ = nullptr;
+        st_host_ = nullptr;
+        st_cap_ = 0;
+        const size_t want = (size_t)std::max(1, n) + (size_t)n / 2;
+        if ((e = hipMalloc((void**)&st_dev_, want * sizeof(SolveState))) != hipSuccess) {
+            st_dev_ = nullptr;
+            return hip_fail(e, "batch states");
+        }
+        if ((e = hipHostMalloc((void**)&st_host_, want * sizeof(SolveState), hipHostMallocDefault)) != hipSuccess) {
+            st_host_ = nullptr;
+            return hip_fail(e, "batch states");
+        }
+        st_cap_ = want;
+    }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "batch tables");
     return DL_OK;
 }
@@ -140,8 +176,9 @@ hipError_t BatchRunner::states(hipStream_t s, std::vector<SolveState>& out)
     out.resize(probs_.size());
     hipError_t e = launch_gather_states(atab_[0], (int)probs_.size(), st_dev_, s);
     if (e == hipSuccess && !out.empty())
-        e = hipMemcpyAsync(out.data(), st_dev_, out.size() * sizeof(SolveState), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(st_host_, st_dev_, out.size() * sizeof(SolveState), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !out.empty()) std::memcpy(out.data(), st_host_, out.size() * sizeof(SolveState));
     return e;
 }
 

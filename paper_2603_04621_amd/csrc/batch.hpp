@@ -44,7 +44,9 @@ private:
     int* ndone_dev_ = nullptr;
     int* ndone_host_ = nullptr;
     dl::SolveState* st_dev_ = nullptr;
+    dl::SolveState* st_host_ = nullptr;   // pinned copy of st_dev_
     size_t st_cap_ = 0;
+    size_t cap_[7] = {0, 0, 0, 0, 0, 0, 0};   // allocated entries of the seven tables
 };
 
 }  // namespace dlh
