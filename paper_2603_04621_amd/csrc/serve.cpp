@@ -9,8 +9,11 @@
 //              per million nonzeros, so one loader would cap admissions);
 //   scheduler  runs ticks of kTick iterations (gap test on the last) over all
 //              active requests with the batched fused launches, retires the
-//              finished ones (lambda copied to host, memory released) and
-//              adds the ready ones at the next tick boundary.
+//              finished ones (lambda copied to host) and adds the ready ones at
+//              the next tick boundary;
+//   reaper     releases the device memory of retired requests (freeing can
+//              wait on the whole device, so the scheduler does not do it) and
+//              returns their bytes to the budget.
 // A request's iterates do not depend on what it shares a tick with.
 #include <hip/hip_runtime.h>
 
@@ -81,6 +84,17 @@ struct dl_server {
     uint64_t next_ticket = 1;
     std::vector<std::thread> loaders;
     std::thread scheduler;
+    // retired problems waiting to be freed, each with its lambda buffer, its
+    // budget bytes and whether its stream is known to be idle
+    struct Retired {
+        dl_problem* prob;
+        double* lam_dev;
+        size_t bytes;
+        bool idle;
+    };
+    std::deque<Retired> reap;
+    bool sched_done = false;
+    std::thread reaper;
 
     double now() const
     {
@@ -239,18 +253,16 @@ static void scheduler_main(dl_server* S)
             } else {
                 res.status = DL_ERR_DEVICE;
             }
-            // its work ran on this stream, which the copy above waited for
-            if (idle) dlh::destroy_idle(r->prob);
-            else dl_problem_destroy(r->prob);
-            r->prob = nullptr;
-            (void)hipFree(r->lam_dev);
-            r->lam_dev = nullptr;
+            // its work ran on this stream, which the copy above waited for;
+            // the reaper frees it and returns its bytes to the budget
             std::lock_guard<std::mutex> lk(S->mu);
+            S->reap.push_back({r->prob, r->lam_dev, r->est_bytes, idle});
+            r->prob = nullptr;
+            r->lam_dev = nullptr;
             r->t_done = S->now();
             res.seconds = r->t_done - r->t_start;
             r->state = 4;
             S->slots_used -= 1;
-            S->used -= r->est_bytes;
             S->cv.notify_all();
         }
         if (!fin.empty()) {
@@ -259,7 +271,35 @@ static void scheduler_main(dl_server* S)
         }
     }
     br.release();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->sched_done = true;
+        S->cv.notify_all();
+    }
     if (s) (void)hipStreamDestroy(s);
+}
+
+static void reaper_main(dl_server* S)
+{
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        dl_server::Retired x;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return !S->reap.empty() || S->sched_done; });
+            if (S->reap.empty()) break;   // the scheduler has exited and nothing is left
+            x = S->reap.front();
+            S->reap.pop_front();
+        }
+        if (x.prob) {
+            if (x.idle) dlh::destroy_idle(x.prob);
+            else dl_problem_destroy(x.prob);
+        }
+        if (x.lam_dev) (void)hipFree(x.lam_dev);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->used -= x.bytes;
+        S->cv.notify_all();
+    }
 }
 
 extern "C" dl_status dl_server_create(size_t hbm_budget_bytes, int32_t max_slots, dl_server** out)
@@ -272,6 +312,7 @@ extern "C" dl_status dl_server_create(size_t hbm_budget_bytes, int32_t max_slots
     S->t0 = std::chrono::steady_clock::now();
     for (int i = 0; i < kLoaders; ++i) S->loaders.emplace_back(loader_main, S);
     S->scheduler = std::thread(scheduler_main, S);
+    S->reaper = std::thread(reaper_main, S);
     *out = S;
     return DL_OK;
 }
@@ -381,6 +422,7 @@ extern "C" dl_status dl_server_destroy(dl_server* S)
     }
     for (auto& t : S->loaders) t.join();
     S->scheduler.join();
+    S->reaper.join();   // exits once the scheduler is done and every retired problem is freed
     for (auto& kv : S->all) {
         if (kv.second->prob) dl_problem_destroy(kv.second->prob);
         if (kv.second->lam_dev) (void)hipFree(kv.second->lam_dev);
