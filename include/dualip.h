@@ -250,6 +250,9 @@ dl_status dl_server_poll(dl_server* s, uint64_t ticket, int32_t* done, dl_solve_
  * completion of a finished, not yet collected ticket. */
 dl_status dl_server_times(dl_server* s, uint64_t ticket, double* t_submit, double* t_start,
                           double* t_done);
+/* Stops admissions and drops queued requests, lets running ones finish,
+ * frees all of the server's device memory and joins its threads.
+ * Uncollected results are discarded. */
 dl_status dl_server_destroy(dl_server* s);
 
 /* Layout and size figures of a created problem. */
