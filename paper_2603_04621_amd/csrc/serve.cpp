@@ -7,8 +7,9 @@
 //              iteration state -- while the device keeps iterating the
 //              admitted ones (building a layout is host work of about 15 ms
 //              per million nonzeros, so one loader would cap admissions);
-//   scheduler  runs ticks of kTick iterations (gap test on the last) over all
-//              active requests with the batched fused launches, retires the
+//   scheduler  runs kTicksPerSync ticks of kTick iterations (gap test on the
+//              last of each) over all active requests with the batched fused
+//              launches, then reads their states back, retires the
 //              finished ones (lambda copied to host) and adds the ready ones at
 //              the next tick boundary;
 //   reaper     releases the device memory of retired requests (freeing can
@@ -37,6 +38,11 @@ using dlh::set_error;
 namespace {
 
 constexpr int kTick = 10;     // iterations per tick; the gap is tested on the last
+// ticks enqueued between two state read-backs: the device idles while the
+// host reads states and enqueues the next launches, so fewer read-backs keep
+// it busier; a request that stops in the first tick skips the second (its
+// launches return at once) and leaves one tick later
+constexpr int kTicksPerSync = 2;
 constexpr int kLoaders = 4;   // concurrent problem builds
 
 struct Request {
@@ -218,7 +224,8 @@ static void scheduler_main(dl_server* S)
             changed = false;
         }
         hipError_t e = hipSuccess;
-        for (int q = 0; q < kTick && e == hipSuccess; ++q) e = br.enqueue_iteration(q == kTick - 1 ? 1 : 0, s);
+        for (int q = 0; q < kTick * kTicksPerSync && e == hipSuccess; ++q)
+            e = br.enqueue_iteration(q % kTick == kTick - 1 ? 1 : 0, s);
         if (e == hipSuccess) e = br.states(s, states);
         std::vector<Request*> keep, fin;
         for (size_t k = 0; k < active.size(); ++k) {
