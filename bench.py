@@ -6,7 +6,13 @@ Zipf(1.1) destinations, FP32-stored a and c, FP64 arithmetic and scalars).
 One step = one full iteration of the hot path: the fused gradient pass
 (gather, projection, per-destination sums), the FP64 reduction, and the
 ascent step with the gap test every 10 iterations.  Inputs are resident in
-HBM before the timed region.  Prints one JSON line.
+HBM before the timed region.  Prints one JSON line, which also carries the
+roofline of the gradient kernel, the CPU oracle's rate on one host core
+(cpu_baseline) and a multi-core OpenMP implementation's rate on all host
+cores (cpu_parallel_baseline).  --config heavy measures the heavy-tailed
+mixed-projection workload instead; --systems adds batched solves and the
+served stream (with a sweep of lower arrival rates); --ablations adds the
+preconditioning and continuation ablations.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--sources I]
 """
