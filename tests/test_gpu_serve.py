@@ -52,6 +52,47 @@ def test_served_results_equal_solo():
         same_solve(k, lam_solo, r_solo, lam_srv, r_srv, s)
 
 
+def test_served_mixed_kernel_groups_equal_solo():
+    """Requests that need different gradient kernels (FP32 and BF16 storage,
+    per-edge primal scales, rows beyond LDS) share the server's ticks; each
+    result equals the request's solo solve, and the memory of every retired
+    request returns to the budget (the budget holds the largest request and
+    one more, so the later ones are admitted only as earlier ones retire)."""
+    from paper_2603_04621_amd.api import Problem, Server, SolveSettings
+    torch.cuda.set_device(0)
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=3, stage_iters=300, stage_tol=1e-3,
+                      tol_rel_gap=1e-4, max_iters=1500, check_every=10, max_step=1e-1,
+                      init_step=1e-3)
+    reqs = [(I.serve_member(20_000, 0, capacity="greedy"), "f32", {}),
+            (I.serve_member(30_000, 1, capacity="greedy"), "bf16", {}),
+            (I.serve_member(25_000, 2, capacity="greedy"), "f32", {"primal_scale": 1}),
+            (I.heavy(I=30_000, J=16_000, dmax=300, capacity="greedy"), "f32", {}),
+            (I.serve_member(15_000, 3, capacity="greedy"), "bf16", {})]
+    solo = []
+    for x, st, po in reqs:
+        with Problem(x, storage=st, **po) as p:
+            lam, r = p.solve(s)
+            solo.append((lam.cpu().numpy(), r))
+    srv = Server(hbm_budget_bytes=35e6, max_slots=3)   # the largest request plus one more
+    tickets = [srv.submit(x, s, storage=st, **po) for x, st, po in reqs]
+    res = {}
+    t_end = time.time() + 120
+    while len(res) < len(tickets) and time.time() < t_end:
+        for t in tickets:
+            if t not in res:
+                out = srv.poll(t)
+                if out is not None:
+                    res[t] = out
+        time.sleep(0.001)
+    srv.close()
+    assert len(res) == len(tickets)
+    from test_gpu_batch import same_solve
+    for k, t in enumerate(tickets):
+        r_srv, lam_srv, _ = res[t]
+        lam_solo, r_solo = solo[k]
+        same_solve(k, lam_solo, r_solo, lam_srv, r_srv, s)
+
+
 def test_server_rejects_oversized_request():
     from paper_2603_04621_amd import _lib as L
     from paper_2603_04621_amd.api import Server, SolveSettings
