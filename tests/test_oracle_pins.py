@@ -571,3 +571,149 @@ def test_secant_lipschitz_estimate_on_exact_quadratic(oracle_lib):
     k_last = int(moving[-1]) + 1          # uses the last moving pair
     assert k_last >= 3
     np.testing.assert_allclose(r.trace[1:k_last + 1, 2], gamma, rtol=1e-9)
+
+
+def test_fista_golden_sequence_is_self_consistent():
+    """The stored FISTA sequence obeys its defining identities (Beck and
+    Teboulle 2009): t_0 = 1, t_1 is the golden ratio, t_{k+1}^2 - t_{k+1} =
+    t_k^2, t_k >= (k+2)/2 (their Lemma 4.3, shifted to a 0-based count) and
+    beta_k = (t_k - 1)/t_{k+1}."""
+    with open(os.path.join(HERE, "golden", "fista_sequence.json")) as f:
+        fs = json.load(f)
+    t = np.array(fs["t"])
+    beta = np.array(fs["beta"])
+    assert t[0] == 1.0
+    assert t[1] == pytest.approx((1 + 5 ** 0.5) / 2, rel=1e-15)
+    np.testing.assert_allclose(t[1:] ** 2 - t[1:], t[:-1] ** 2, rtol=1e-14)
+    assert np.all(t >= (np.arange(len(t)) + 2) / 2)
+    np.testing.assert_allclose(beta, (t[:-1] - 1) / t[1:], rtol=1e-14, atol=1e-16)
+
+
+def two_curvature_quadratic(seed):
+    """Quadratic regime (every projection inactive, as in
+    quadratic_regime_instance) without row normalization: rows of even index
+    have norm 1, odd rows norm 1/2, so A A' = diag(n_j^2) and the dual is the
+    separable quadratic g(lam) = g* - 1/2 sum_j h_j (lam_j - lam*_j)^2 with
+    two curvatures h_j = n_j^2/gamma.  b = (-A c - diag(n^2) lam*)/gamma puts
+    the maximiser at lam* > 0."""
+    inst = I.random_small(seed, I=60, J=8, dmax=5, box_frac=1.0)
+    rng = np.random.default_rng(seed)
+    ssq = np.bincount(inst.dst, weights=inst.a ** 2, minlength=inst.m)
+    assert np.all(ssq > 0)
+    nrm = np.where(np.arange(inst.m) % 2 == 0, 1.0, 0.5)
+    inst.a = inst.a * nrm[inst.dst] / np.sqrt(ssq[inst.dst])
+    inst.c = -10.0 - rng.uniform(0, 1, size=inst.n)
+    inst.upper = np.full(inst.n, 1e12)
+    gamma = 0.05
+    lam_star = rng.uniform(0.2, 0.6, size=inst.m)
+    A = inst.dense()
+    inst.b = (-(A @ inst.c) - nrm ** 2 * lam_star) / gamma
+    return inst, A, gamma, lam_star, nrm ** 2 / gamma
+
+
+def test_fista_momentum_trajectory_on_separable_quadratic(oracle_lib):
+    """Pins the momentum of the accelerated loop (coefficient and t-update).
+
+    With a fixed step eta below 1/L and every projection inactive, each
+    coordinate's error e = lam - lam* follows a scalar linear recursion:
+    the step multiplies it by (1 - eta h_j), and the momentum point is
+    y = lam_+ + beta_k (lam_+ - lam) with the stored FISTA coefficients.
+    The expected g(y_k) = g* - 1/2 sum_j h_j e_j(y_k)^2 follows from that
+    recursion alone; the oracle evaluates gradients of the full LP instead.
+    A wrong coefficient ((t-1)/(t+1), or t_+ = (1 + sqrt(1 + t^2))/2) moves
+    g(y_2) and every later value by far more than the tolerance."""
+    O = oracle_lib
+    with open(os.path.join(HERE, "golden", "fista_sequence.json")) as f:
+        beta = np.array(json.load(f)["beta"])
+    inst, A, gamma, lam_star, h = two_curvature_quadratic(93)
+    gstar = quad_g(inst, A, gamma, lam_star)
+    eta = gamma / 3.0                       # below 1/L = gamma / max n_j^2
+    K = len(beta)                           # evaluations y_0 .. y_{K-1}
+    r = O.solve(inst, O.SolveOpts(gamma0=gamma, gamma_final=gamma, max_iters=K,
+                                  check_every=0, max_step=eta, init_step=eta, adaptive=0,
+                                  row_normalize=0))
+    # scalar recursion per coordinate, errors relative to lam*
+    e_lam = -lam_star.copy()                # lam_0 = 0
+    e_y = -lam_star.copy()                  # y_0 = 0
+    expect = []
+    for k in range(K):
+        expect.append(-0.5 * np.sum(h * e_y ** 2))
+        e_new = (1.0 - eta * h) * e_y
+        e_y = e_new + beta[k] * (e_new - e_lam)
+        e_lam = e_new
+        assert np.all(lam_star + e_y > 0)   # projections onto lam >= 0 stay inactive
+    expect = np.array(expect)
+    got = r.trace[:, 0] - gstar
+    assert got[-1] < -1e-3                  # still far from lam*: momentum matters
+    np.testing.assert_allclose(got, expect, rtol=1e-7)
+    # the returned point is the last evaluated one, y_{K-1}
+    e_last = -lam_star.copy()
+    e_l = -lam_star.copy()
+    for k in range(K - 1):
+        e_new = (1.0 - eta * h) * e_last
+        e_last, e_l = e_new + beta[k] * (e_new - e_l), e_new
+    np.testing.assert_allclose(r.lam, lam_star + e_last, rtol=1e-9)
+
+
+def test_momentum_restarts_at_gamma_stage(oracle_lib):
+    """At a stage change the momentum restarts (t = 1, y = lam_+): the first
+    step of the new stage carries no momentum.  On the separable quadratic a
+    two-stage run with stage_iters = 3 gives, in stage 1, the same error
+    recursion as a fresh run started from the stage-0 iterate."""
+    O = oracle_lib
+    with open(os.path.join(HERE, "golden", "fista_sequence.json")) as f:
+        beta = np.array(json.load(f)["beta"])
+    inst, A, gamma, lam_star, h = two_curvature_quadratic(94)
+    # both stages at the same gamma, so the quadratic does not change
+    eta = gamma / 3.0
+    r = O.solve(inst, O.SolveOpts(gamma0=gamma, gamma_final=gamma, n_stages=2, stage_iters=3,
+                                  max_iters=7, check_every=0, max_step=eta, init_step=eta,
+                                  adaptive=0, row_normalize=0))
+    gstar = quad_g(inst, A, gamma, lam_star)
+    e_lam = -lam_star.copy()
+    e_y = -lam_star.copy()
+    expect, kb = [], 0
+    for k in range(7):
+        expect.append(-0.5 * np.sum(h * e_y ** 2))
+        e_new = (1.0 - eta * h) * e_y
+        if k == 2:                          # stage advance after 3 iterations
+            e_y, e_lam, kb = e_new.copy(), e_new, 0
+            continue
+        e_y = e_new + beta[kb] * (e_new - e_lam)
+        e_lam = e_new
+        kb += 1
+    np.testing.assert_allclose(r.trace[:, 0] - gstar, expect, rtol=1e-7)
+    np.testing.assert_array_equal(r.trace[:, 4], [0, 0, 0, 1, 1, 1, 1])
+
+
+def test_momentum_point_is_projected_to_nonnegative(oracle_lib):
+    """The momentum point y is projected onto lam >= 0, so every evaluated
+    g(y) is a valid dual bound.  On the separable quadratic with the
+    unconstrained maximiser negative in half the coordinates and a warm
+    start at lam = 1, the step drives those coordinates to 0 and the momentum
+    would push y below 0; the expected values clip y at 0, and g(y) is the
+    closed-form quadratic at the clipped point."""
+    O = oracle_lib
+    with open(os.path.join(HERE, "golden", "fista_sequence.json")) as f:
+        beta = np.array(json.load(f)["beta"])
+    inst, A, gamma, lam_pos, h = two_curvature_quadratic(95)
+    lam_star = lam_pos * np.where(np.arange(inst.m) % 4 < 2, 1.0, -1.0)
+    nrm2 = h * gamma
+    inst.b = (-(A @ inst.c) - nrm2 * lam_star) / gamma
+    gstar = quad_g(inst, A, gamma, lam_star)
+    eta = gamma / 1.5
+    K = len(beta)
+    lam0 = np.ones(inst.m)
+    r = O.solve(inst, O.SolveOpts(gamma0=gamma, gamma_final=gamma, max_iters=K,
+                                  check_every=0, max_step=eta, init_step=eta, adaptive=0,
+                                  row_normalize=0), lam0=lam0)
+    lam, y = lam0.copy(), lam0.copy()
+    expect, clipped = [], False
+    for k in range(K):
+        expect.append(-0.5 * np.sum(h * (y - lam_star) ** 2))
+        ln = np.maximum(0.0, y + eta * h * (lam_star - y))
+        z = ln + beta[k] * (ln - lam)
+        clipped |= bool(np.any(z < 0))
+        y, lam = np.maximum(0.0, z), ln
+    assert clipped                          # the projection of y is exercised
+    np.testing.assert_allclose(r.trace[:, 0] - gstar, expect, rtol=1e-7)
