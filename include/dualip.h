@@ -181,8 +181,25 @@ dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, double gamma, do
  *                        (ordinary iterations) and check_kernel_ms (gap-check
  *                        iterations).
  *   trace_host           NULL or [max_iters * DL_TRACE_W] FP64 rows:
- *                        g, rel_gap (NaN off-check), eta, gamma, stage, |G'|. */
+ *                        g, rel_gap (NaN off-check), eta, gamma, stage, |G'|.
+ *   preset               how max_step and init_step are set (dl_preset):
+ *                        DL_PRESET_CUSTOM uses the two fields as given; the
+ *                        other presets overwrite them per problem from
+ *                        gamma0 and |A'|^2, the squared spectral norm of the
+ *                        matrix the solver iterates on (after primal scaling
+ *                        and, when on, row normalization; dl_problem_info
+ *                        reports it), so that L = |A'|^2/gamma is the dual's
+ *                        Lipschitz constant (Appendix A, Lemma 2):
+ *                          DL_PRESET_PAPER    max_step = 0.1 gamma0/|A'|^2,
+ *                                             init_step = 1e-3 gamma0/|A'|^2:
+ *                                             at gamma0 = 0.01 and |A'| = 1
+ *                                             these are Appendix B's fixed
+ *                                             1e-3 and 1e-5;
+ *                          DL_PRESET_NATURAL  max_step = gamma0/|A'|^2 = 1/L
+ *                                             (the classical safe step),
+ *                                             init_step = 1e-2 gamma0/|A'|^2. */
 #define DL_TRACE_W 6
+typedef enum { DL_PRESET_CUSTOM = 0, DL_PRESET_PAPER = 1, DL_PRESET_NATURAL = 2 } dl_preset;
 typedef struct {
     double gamma0, gamma_final;
     int32_t n_stages, momentum;
@@ -193,12 +210,22 @@ typedef struct {
     int32_t adaptive, warm_start;
     int32_t graph_iters, time_kernels;
     double* trace_host;
+    int32_t preset;
+    int32_t reserved;        /* set to 0 */
 } dl_solve_opts;
 
 /* Defaults: gamma0 = gamma_final = 0.01, one stage, momentum and adaptive on,
  * tol 1e-4 checked every 10 iterations, max_iters 10000, max_step = gamma0,
- * init_step = 1e-2 gamma0 (the paper's 1e-3 / 1e-5 ratio of Appendix B). */
+ * init_step = 1e-2 gamma0 (the paper's 1e-3 / 1e-5 ratio of Appendix B),
+ * preset DL_PRESET_CUSTOM. */
 void dl_solve_opts_init(dl_solve_opts* opts);
+
+/* Host only: resolves opts->preset for a problem whose iteration matrix has
+ * squared norm anorm2 (> 0, finite): writes max_step and init_step as listed
+ * under `preset` above; DL_PRESET_CUSTOM leaves them.  dl_solve,
+ * dl_batch_solve and the server call it with each problem's own |A'|^2.
+ * DL_ERR_INVALID_ARG for an unknown preset or anorm2 <= 0. */
+dl_status dl_solve_opts_apply_preset(dl_solve_opts* opts, double anorm2);
 
 typedef struct {
     dl_status status;
@@ -269,6 +296,9 @@ typedef struct {
     int32_t seg_rmax;          /* largest rows per lane of multi-lane blocks      */
     int32_t chunks_per_cu;     /* workgroups of the gradient kernel per CU        */
     int32_t tuned;             /* 1 when the layout was picked by autotune        */
+    double anorm2;             /* |A'|^2 of the iteration matrix (see preset): 1
+                                  with row normalization and one family, else
+                                  max_j |(A D_v^{-1})_j*|^2 (rows are orthogonal)  */
 } dl_problem_info;
 dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info);
 

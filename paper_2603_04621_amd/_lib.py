@@ -20,6 +20,8 @@ DL_ERR_NOT_FOUND = 8
 DL_CSC, DL_CSR = 0, 1
 DL_F64, DL_F32, DL_BF16_AC = 0, 1, 2
 DL_TRACE_W = 6
+DL_PRESET_CUSTOM, DL_PRESET_PAPER, DL_PRESET_NATURAL = 0, 1, 2
+PRESET = {"custom": DL_PRESET_CUSTOM, "paper": DL_PRESET_PAPER, "natural": DL_PRESET_NATURAL}
 
 STORAGE = {"f64": DL_F64, "f32": DL_F32, "bf16": DL_BF16_AC}
 
@@ -51,7 +53,7 @@ class SolveOpts(ctypes.Structure):
                 ("tol_rel_gap", c_dbl), ("max_iters", c_i64), ("check_every", c_i64),
                 ("max_step", c_dbl), ("init_step", c_dbl), ("adaptive", c_i32),
                 ("warm_start", c_i32), ("graph_iters", c_i32), ("time_kernels", c_i32),
-                ("trace_host", c_ptr)]
+                ("trace_host", c_ptr), ("preset", c_i32), ("reserved", c_i32)]
 
 
 class SolveResult(ctypes.Structure):
@@ -66,13 +68,14 @@ class ProblemInfo(ctypes.Structure):
     _fields_ = [(k, c_i64) for k in ("m", "n", "num_blocks", "lane_groups", "seg_groups",
                                      "wg_blocks", "chunks", "lds_rows", "stream_bytes",
                                      "device_bytes")] + [(k, c_i32) for k in (
-                    "storage", "has_box", "lane_cap", "seg_rmax", "chunks_per_cu", "tuned")]
+                    "storage", "has_box", "lane_cap", "seg_rmax", "chunks_per_cu", "tuned")] + [
+                    ("anorm2", c_dbl)]
 
 
 # every symbol include/dualip.h declares
 EXPORTS = [
     "dl_problem_opts_init", "dl_problem_validate", "dl_problem_create", "dl_problem_destroy",
-    "dl_dual_grad", "dl_solve_opts_init", "dl_solve", "dl_batch_solve", "dl_server_create",
+    "dl_dual_grad", "dl_solve_opts_init", "dl_solve_opts_apply_preset", "dl_solve", "dl_batch_solve", "dl_server_create",
     "dl_server_submit", "dl_server_poll", "dl_server_times", "dl_server_destroy",
     "dl_problem_get_info", "dl_time_grad_kernel", "dl_status_str", "dl_last_error",
 ]
@@ -102,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.dl_dual_grad.argtypes = [c_ptr, c_ptr, c_dbl, c_ptr, c_ptr, P(Eval), c_ptr]
         L.dl_solve_opts_init.argtypes = [P(SolveOpts)]
         L.dl_solve_opts_init.restype = None
+        L.dl_solve_opts_apply_preset.argtypes = [P(SolveOpts), c_dbl]
+        L.dl_solve_opts_apply_preset.restype = ctypes.c_int
         L.dl_solve.argtypes = [c_ptr, P(SolveOpts), c_ptr, P(SolveResult), c_ptr]
         L.dl_batch_solve.argtypes = [P(c_ptr), c_i32, P(SolveOpts), P(c_ptr), P(SolveResult),
                                      c_ptr]

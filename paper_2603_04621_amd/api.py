@@ -70,6 +70,17 @@ def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: in
     return o, keep
 
 
+def apply_preset(settings: "SolveSettings", anorm2: float = 1.0) -> "SolveSettings":
+    """The settings with max_step and init_step resolved by the C library's
+    dl_solve_opts_apply_preset for an iteration matrix of squared norm
+    anorm2 (host only)."""
+    o = settings.to_c(None)
+    L.check(L.lib().dl_solve_opts_apply_preset(ctypes.byref(o), float(anorm2)),
+            "dl_solve_opts_apply_preset")
+    return SolveSettings(**{**settings.__dict__, "max_step": o.max_step,
+                            "init_step": o.init_step})
+
+
 def validate(inst, layout: str = "csc", **opts) -> int:
     """dl_problem_validate (host only).  Returns the status code."""
     hd = _HostDesc(inst, layout)
@@ -96,6 +107,7 @@ class SolveSettings:
     graph_iters: int = 0
     time_kernels: int = 0
     trace: bool = False
+    preset: str = "custom"          # "custom" | "paper" | "natural" (dl_preset)
 
     def to_c(self, trace_buf=None) -> L.SolveOpts:
         o = L.SolveOpts()
@@ -104,6 +116,7 @@ class SolveSettings:
                   "tol_rel_gap", "max_iters", "check_every", "max_step", "init_step",
                   "adaptive", "warm_start", "graph_iters", "time_kernels"):
             setattr(o, k, getattr(self, k))
+        o.preset = L.PRESET[self.preset]
         o.trace_host = None if trace_buf is None else trace_buf.ctypes.data
         return o
 

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -100,6 +101,29 @@ extern "C" void dl_solve_opts_init(dl_solve_opts* o)
     o->graph_iters = 0;
     o->time_kernels = 0;
     o->trace_host = nullptr;
+    o->preset = DL_PRESET_CUSTOM;
+    o->reserved = 0;
+}
+
+extern "C" dl_status dl_solve_opts_apply_preset(dl_solve_opts* o, double anorm2)
+{
+    if (!o) { set_error("opts is NULL"); return DL_ERR_INVALID_ARG; }
+    if (!(anorm2 > 0.0) || !std::isfinite(anorm2)) { set_error("anorm2 must be positive and finite"); return DL_ERR_INVALID_ARG; }
+    if (!(o->gamma0 > 0.0) || !std::isfinite(o->gamma0)) { set_error("gamma0 must be positive"); return DL_ERR_INVALID_ARG; }
+    // step cap and first step as fractions of 1/L at gamma0, L = |A'|^2 / gamma0
+    switch (o->preset) {
+    case DL_PRESET_CUSTOM: return DL_OK;
+    case DL_PRESET_PAPER:
+        o->max_step = 0.1 * o->gamma0 / anorm2;
+        o->init_step = 1e-3 * o->gamma0 / anorm2;
+        return DL_OK;
+    case DL_PRESET_NATURAL:
+        o->max_step = o->gamma0 / anorm2;
+        o->init_step = 1e-2 * o->gamma0 / anorm2;
+        return DL_OK;
+    }
+    set_error("unknown preset %d", (int)o->preset);
+    return DL_ERR_INVALID_ARG;
 }
 
 // ---------------------------------------------------------------------------
@@ -461,6 +485,13 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         bD[j] = d->b[o];
         Dv[j] = (opts.row_normalize && r2[o] > 0.0) ? 1.0 / std::sqrt(r2[o]) : 1.0;
     }
+    // one family: A D_v^{-1} has orthogonal rows, so |A'|^2 is the largest
+    // squared row norm (1 after row normalization, empty rows aside)
+    {
+        double mx = 0.0;
+        for (int64_t j = 0; j < m; ++j) mx = std::max(mx, opts.row_normalize ? (r2[j] > 0.0 ? 1.0 : 0.0) : r2[j]);
+        p->anorm2 = mx > 0.0 ? mx : 1.0;
+    }
     for (int64_t i = 0; i < d->num_blocks && !p->has_box; ++i) p->has_box = d->block_proj[i] == DL_PROJ_BOX;
 
     // work items and chunks
@@ -576,8 +607,7 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         if (e != hipSuccess) { st = hip_fail(e, "upload"); free_problem(p); return st; }
         e = hipHostMalloc((void**)&p->st_host, 2 * sizeof(SolveState), hipHostMallocDefault);
         if (e != hipSuccess) { p->st_host = nullptr; st = hip_fail(e, "pinned state"); free_problem(p); return st; }
-        e = set_grad_attributes(std::max(grad_lds_bytes(p->K, p->Kc, false, p->K < p->J),
-                                         grad_lds_bytes(p->K, p->Kc, true, p->K < p->J)));
+        e = dlh::ensure_grad_attributes(p->device);
         if (e != hipSuccess) { st = hip_fail(e, "kernel LDS attribute"); free_problem(p); return st; }
     }
 #undef ALLOC
@@ -722,6 +752,22 @@ extern "C" dl_status dl_problem_destroy(dl_problem* p)
 }
 
 namespace dlh {
+// The gradient kernels' dynamic-LDS limit is a process-wide attribute of each
+// kernel.  It is raised once per device to the device's whole LDS (every
+// problem's need fits under it) and never lowered, under a lock, so problems
+// created concurrently (the server's loader threads) cannot shrink it below
+// what a running launch uses.
+hipError_t ensure_grad_attributes(int device)
+{
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), device) != done.end()) return hipSuccess;
+    const hipError_t e = set_grad_attributes(device_max_lds(device));
+    if (e == hipSuccess) done.push_back(device);
+    return e;
+}
+
 void destroy_idle(dl_problem* p)
 {
     if (p) free_problem(p);
@@ -747,6 +793,7 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* i
     info->seg_rmax = p->seg_rmax;
     info->chunks_per_cu = p->chunk_mult;
     info->tuned = p->tuned;
+    info->anorm2 = p->anorm2;
     return DL_OK;
 }
 
@@ -862,11 +909,15 @@ dl_status check_solve_opts(const dl_solve_opts* o)
     if (!(o->max_step > 0.0) || !(o->init_step > 0.0)) { set_error("steps must be positive"); return DL_ERR_INVALID_ARG; }
     if (std::isnan(o->tol_rel_gap) || !(o->stage_tol >= 0.0)) { set_error("invalid tolerance"); return DL_ERR_INVALID_ARG; }
     if (o->graph_iters < 0) { set_error("graph_iters must be >= 0"); return DL_ERR_INVALID_ARG; }
+    if (o->preset < DL_PRESET_CUSTOM || o->preset > DL_PRESET_NATURAL) { set_error("unknown preset %d", (int)o->preset); return DL_ERR_INVALID_ARG; }
     return DL_OK;
 }
 
-SolveParams make_params(const dl_solve_opts* o)
+SolveParams make_params(const dl_solve_opts* o_in, const dl_problem* p)
 {
+    dl_solve_opts ob = *o_in;
+    const dl_solve_opts* o = &ob;
+    (void)dl_solve_opts_apply_preset(&ob, p->anorm2);   // options were checked before
     SolveParams P;
     std::memset(&P, 0, sizeof P);
     P.gamma0 = o->gamma0;

@@ -219,15 +219,17 @@ extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, con
             if (ps[q] == ps[k]) { set_error("problem %d appears twice in the batch", k); return DL_ERR_INVALID_ARG; }
     }
     hipStream_t s = (hipStream_t)hip_stream;
-    const SolveParams prm = dlh::make_params(o);
+    std::vector<SolveParams> prms((size_t)count);
+    for (int k = 0; k < count; ++k) prms[(size_t)k] = dlh::make_params(o, ps[k]);
     for (int k = 0; k < count; ++k) {
         dl_problem* p = ps[k];
+        const SolveParams& prm = prms[(size_t)k];
         TRY(launch_solve_init(p->st, prm, o->warm_start ? lambdas[k] : nullptr, p->orig, p->D, p->J, p->lam, p->y,
                               p->yp, p->G, p->Gp, p->lam_eval, s),
             "init kernel");
     }
     dlh::BatchRunner br;
-    st = br.build(ps, std::vector<SolveParams>(count, prm), s);
+    st = br.build(ps, prms, s);
     if (st != DL_OK) return st;
     const int64_t N = o->max_iters;
     int64_t seg = o->graph_iters > 0 ? o->graph_iters : (o->check_every > 0 ? o->check_every : 16);

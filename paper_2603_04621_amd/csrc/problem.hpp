@@ -14,6 +14,7 @@ struct dl_problem {
     int64_t m = 0, n = 0, nblocks = 0;
     int storage = 1;
     int has_box = 0, has_w = 0, solve_ok = 1;
+    double anorm2 = 1.0;               // |A'|^2 of the iteration matrix (presets)
     int J = 0, K = 0;                  // rows; rows resident in LDS
     int Kc = 0;                        // rows of the check-pass c x, v^2 x^2 sums in LDS
     int nchunks = 0, nitems = 0, nblk2 = 0;
@@ -70,8 +71,13 @@ hipError_t enqueue_iteration(dl_problem* p, const dl::SolveParams& prm, int chec
 // (no device-wide synchronization, unlike dl_problem_destroy)
 void destroy_idle(dl_problem* p);
 
+// raises the gradient kernels' dynamic-LDS limit to the device maximum, once
+// per device (thread-safe)
+hipError_t ensure_grad_attributes(int device);
+
 dl_status check_solve_opts(const dl_solve_opts* o);
-dl::SolveParams make_params(const dl_solve_opts* o);
+// solve parameters of problem p (its preset resolved with p's |A'|^2)
+dl::SolveParams make_params(const dl_solve_opts* o, const dl_problem* p);
 bool is_check_iter(const dl_solve_opts* o, int64_t k);
 
 }  // namespace dlh

@@ -108,14 +108,33 @@ struct dl_server {
     }
 };
 
+// An upper bound of the device bytes dl_problem_create will hold for the
+// request, by the same rules it allocates with: the edge stream (a, c, dst,
+// perm; box bounds whenever any block is a box; 1/v^2 with primal scaling),
+// at most one work item per block, up to two chunks per compute unit (the
+// autotuner's largest choice) of partial sums for at most 16384 LDS rows, the
+// row vectors, the request's lambda buffer and its share of the batched
+// argument tables.  Once the problem exists the admission charge is lowered
+// to its actual footprint.
 static size_t estimate_bytes(const dl_problem_desc* d, const dl_problem_opts* o)
 {
     const size_t es = o->storage == DL_F64 ? 8 : (o->storage == DL_F32 ? 4 : 2);
-    const size_t n = (size_t)d->n, m = (size_t)d->m;
-    size_t bytes = n * (2 * es + 4 + 8) + (d->upper ? 4 * n : 0) + (o->primal_scale ? 4 * n : 0);
-    const size_t nch = std::min<size_t>(256, std::max<size_t>(1, (n + 32767) / 32768));
-    bytes += 3 * nch * std::min<size_t>(m, 16384) * 4 + m * 8 * 14 + (1 << 20);
+    const size_t n = (size_t)d->n, m = (size_t)d->m, nb = (size_t)d->num_blocks;
+    bool has_box = false;
+    for (size_t i = 0; i < nb && !has_box; ++i) has_box = d->block_proj[i] == DL_PROJ_BOX;
+    size_t bytes = n * (2 * es + 4 + 8) + (has_box ? 4 * n : 0) + (o->primal_scale ? 4 * n : 0);
+    bytes += nb * sizeof(Item);
+    const size_t nch = std::min<size_t>(2 * 256, std::max<size_t>(1, (n + 32767) / 32768));
+    bytes += nch * (sizeof(Chunk) + 3 * 8) + 3 * nch * std::min<size_t>(m, 16384) * 4;
+    bytes += m * (8 * 14 + 4) + ((m + 63) / 64) * kRedStride * 8;
+    bytes += m * 8 + 4096 + (1 << 20);
     return bytes;
+}
+
+// the bytes the request actually holds once built
+static size_t actual_bytes(const dl_problem* p, const dl_problem_desc* d)
+{
+    return p->device_bytes + (size_t)d->m * 8 + 4096;
 }
 
 static void loader_main(dl_server* S)
@@ -143,6 +162,7 @@ static void loader_main(dl_server* S)
         dl_status st = dl_problem_create(&r->desc, &r->popts, s, &r->prob);
         hipError_t e = hipSuccess;
         if (st == DL_OK) {
+            r->prm = dlh::make_params(&r->sopts, r->prob);
             e = hipMalloc((void**)&r->lam_dev, (size_t)r->desc.m * sizeof(double));
             if (e == hipSuccess)
                 e = launch_solve_init(r->prob->st, r->prm, nullptr, r->prob->orig, r->prob->D, r->prob->J,
@@ -164,6 +184,10 @@ static void loader_main(dl_server* S)
             S->slots_used -= 1;
             S->used -= r->est_bytes;
         } else {
+            // charge the actual footprint from now on (never above the estimate)
+            const size_t act = std::min(actual_bytes(r->prob, &r->desc), r->est_bytes);
+            S->used -= r->est_bytes - act;
+            r->est_bytes = act;
             r->state = 2;
             S->ready.push_back(r);
         }
@@ -367,7 +391,6 @@ extern "C" dl_status dl_server_submit(dl_server* S, const dl_problem_desc* d, co
     r->sopts.trace_host = nullptr;
     r->sopts.warm_start = 0;
     r->sopts.check_every = kTick;
-    r->prm = dlh::make_params(&r->sopts);
     r->est_bytes = estimate_bytes(d, &popts);
     if (r->est_bytes > S->budget) {
         delete r;

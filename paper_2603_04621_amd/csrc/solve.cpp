@@ -60,7 +60,7 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
     }
     std::memset(out, 0, sizeof *out);
     hipStream_t s = (hipStream_t)hip_stream;
-    const SolveParams prm = dlh::make_params(o);
+    const SolveParams prm = dlh::make_params(o, p);
     Cleanup cl;
     if (o->trace_host && o->max_iters > 0)
         TRY(hipMalloc(&cl.trace, (size_t)o->max_iters * DL_TRACE_W * sizeof(double)), "trace buffer");

@@ -148,3 +148,32 @@ def test_problem_opts_defaults_and_autotune_flag():
     st = L.lib().dl_problem_create(ctypes.byref(hd.desc), ctypes.byref(o), None, ctypes.byref(h))
     assert st == L.DL_ERR_INVALID_ARG and not h.value
     assert "autotune" in L.lib().dl_last_error().decode()
+
+
+def test_solve_presets_host_side():
+    """dl_solve_opts_apply_preset: PAPER reproduces Appendix B's fixed step
+    sizes (max-step 1e-3, initial-step 1e-5 at gamma = 0.01, with |A'| = 1
+    after row normalization of one family); NATURAL gives the classical
+    1/L = gamma/|A'|^2 (Lemma 2's L); both scale with 1/|A'|^2; CUSTOM keeps
+    the caller's values; unknown presets and non-positive norms are
+    rejected."""
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "paper_hyperparameters.json")) as f:
+        hp = json.load(f)
+    s = api.SolveSettings(gamma0=hp["gamma"], max_step=7.0, init_step=3.0, preset="paper")
+    r = api.apply_preset(s, 1.0)
+    assert r.max_step == pytest.approx(hp["max_step_size"], rel=1e-15)
+    assert r.init_step == pytest.approx(hp["initial_step_size"], rel=1e-15)
+    r4 = api.apply_preset(s, 4.0)
+    assert r4.max_step == pytest.approx(hp["max_step_size"] / 4, rel=1e-15)
+    n = api.apply_preset(api.SolveSettings(gamma0=0.05, preset="natural"), 2.0)
+    assert n.max_step == pytest.approx(0.05 / 2.0, rel=1e-15)
+    assert n.init_step == pytest.approx(1e-2 * 0.05 / 2.0, rel=1e-15)
+    c = api.apply_preset(api.SolveSettings(gamma0=0.05, max_step=7.0, init_step=3.0), 9.0)
+    assert (c.max_step, c.init_step) == (7.0, 3.0)
+    o = s.to_c(None)
+    o.preset = 9
+    assert L.lib().dl_solve_opts_apply_preset(ctypes.byref(o), 1.0) == L.DL_ERR_INVALID_ARG
+    o.preset = L.DL_PRESET_PAPER
+    assert L.lib().dl_solve_opts_apply_preset(ctypes.byref(o), 0.0) == L.DL_ERR_INVALID_ARG
+    assert L.lib().dl_solve_opts_apply_preset(ctypes.byref(o), float("nan")) == L.DL_ERR_INVALID_ARG

@@ -93,6 +93,44 @@ def test_served_mixed_kernel_groups_equal_solo():
         same_solve(k, lam_solo, r_solo, lam_srv, r_srv, s)
 
 
+def test_served_request_in_a_mix_matches_oracle():
+    """An FP64 request served together with FP32 and BF16 requests (shared
+    ticks, admissions while it runs) against the CPU oracle's solve of the
+    same LP under the same settings: same stopping iteration, stage and
+    gamma; g, rel_gap and lam within the parity tolerances."""
+    from oracle import oracle as O
+    from paper_2603_04621_amd.api import Server, SolveSettings
+    from test_gpu_batch import assert_matches_oracle, oracle_settings
+    torch.cuda.set_device(0)
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=3, stage_iters=300, stage_tol=1e-3,
+                      tol_rel_gap=1e-4, max_iters=2000, check_every=10, max_step=1e-1,
+                      init_step=1e-3)
+    target = I.serve_member(6_000, 7, capacity="greedy")
+    others = [(I.serve_member(20_000, 8, capacity="greedy"), "f32"),
+              (I.serve_member(9_000, 9, capacity="greedy"), "bf16"),
+              (I.serve_member(30_000, 10, capacity="greedy"), "f32")]
+    srv = Server(hbm_budget_bytes=8e9, max_slots=3)
+    tickets = [srv.submit(others[0][0], s, storage=others[0][1]),
+               srv.submit(target, s, storage="f64")]
+    time.sleep(0.002)
+    tickets += [srv.submit(x, s, storage=st) for x, st in others[1:]]
+    res = {}
+    t_end = time.time() + 120
+    while len(res) < len(tickets) and time.time() < t_end:
+        for t in tickets:
+            if t not in res:
+                out = srv.poll(t)
+                if out is not None:
+                    res[t] = out
+        time.sleep(0.001)
+    srv.close()
+    assert len(res) == len(tickets)
+    r_srv, lam_srv, _ = res[tickets[1]]
+    r_or = O.solve(target, oracle_settings(O, s))
+    assert r_or.converged
+    assert_matches_oracle(r_srv, lam_srv, r_or)
+
+
 def test_server_rejects_oversized_request():
     from paper_2603_04621_amd import _lib as L
     from paper_2603_04621_amd.api import Server, SolveSettings
