@@ -158,6 +158,25 @@ typedef struct {
 dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, double gamma, double* grad_dev,
                        double* x_dev, dl_eval* eval_host, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops or harnesses that forbid hipMalloc): the same
+ * evaluation as dl_dual_grad, with the same arguments, results and errors,
+ * but every intermediate buffer (permuted lambda, chunk partial sums, FP64
+ * accumulators of rows beyond LDS, objective and block partials, scalars) is
+ * taken from one static device array of DL_NOALLOC_SCRATCH_BYTES per device,
+ * held by the library until the process ends.  The call allocates nothing
+ * and makes no hipMalloc/hipFree.  It must be made with the problem's device
+ * current (else DL_ERR_INVALID_ARG).  A problem whose evaluation needs more
+ * scratch than the array holds (roughly 4 B x chunks x LDS rows per partial
+ * plane, 3 planes when eval_host is given, plus 32 B per row) fails with
+ * DL_ERR_UNSUPPORTED before any device work.  All calls on one device share
+ * the array: calls whose stream work overlaps on one device (other streams,
+ * other threads) race and give wrong results; serialize them. */
+#define DL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dl_status dl_dual_grad_noalloc(dl_problem* p, const double* lambda_dev, double gamma,
+                               double* grad_dev, double* x_dev, dl_eval* eval_host,
+                               void* hip_stream);
+
 /* Accelerated dual ascent with gamma continuation (Section 5; Appendix B).
  * Step: lam+ = max(0, y + eta G'), eta = min(eta_max, 1/L^) with the running
  * Lipschitz estimate L^ = |G' - G'_prev| / |y - y_prev| (adaptive = 1) or

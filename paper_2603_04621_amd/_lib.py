@@ -21,6 +21,7 @@ DL_CSC, DL_CSR = 0, 1
 DL_F64, DL_F32, DL_BF16_AC = 0, 1, 2
 DL_TRACE_W = 6
 DL_PRESET_CUSTOM, DL_PRESET_PAPER, DL_PRESET_NATURAL = 0, 1, 2
+DL_NOALLOC_SCRATCH_BYTES = 64 << 20
 PRESET = {"custom": DL_PRESET_CUSTOM, "paper": DL_PRESET_PAPER, "natural": DL_PRESET_NATURAL}
 
 STORAGE = {"f64": DL_F64, "f32": DL_F32, "bf16": DL_BF16_AC}
@@ -78,6 +79,7 @@ EXPORTS = [
     "dl_dual_grad", "dl_solve_opts_init", "dl_solve_opts_apply_preset", "dl_solve", "dl_batch_solve", "dl_server_create",
     "dl_server_submit", "dl_server_poll", "dl_server_times", "dl_server_destroy",
     "dl_problem_get_info", "dl_time_grad_kernel", "dl_status_str", "dl_last_error",
+    "dl_dual_grad_noalloc",
 ]
 
 _LIB = None
@@ -103,6 +105,7 @@ def lib() -> ctypes.CDLL:
         L.dl_problem_create.argtypes = [P(ProblemDesc), P(ProblemOpts), c_ptr, P(c_ptr)]
         L.dl_problem_destroy.argtypes = [c_ptr]
         L.dl_dual_grad.argtypes = [c_ptr, c_ptr, c_dbl, c_ptr, c_ptr, P(Eval), c_ptr]
+        L.dl_dual_grad_noalloc.argtypes = [c_ptr, c_ptr, c_dbl, c_ptr, c_ptr, P(Eval), c_ptr]
         L.dl_solve_opts_init.argtypes = [P(SolveOpts)]
         L.dl_solve_opts_init.restype = None
         L.dl_solve_opts_apply_preset.argtypes = [P(SolveOpts), c_dbl]
@@ -123,7 +126,7 @@ def lib() -> ctypes.CDLL:
         L.dl_last_error.argtypes = []
         L.dl_last_error.restype = ctypes.c_char_p
         for name in ("dl_problem_validate", "dl_problem_create", "dl_problem_destroy",
-                     "dl_dual_grad", "dl_solve", "dl_batch_solve", "dl_server_create",
+                     "dl_dual_grad", "dl_dual_grad_noalloc", "dl_solve", "dl_batch_solve", "dl_server_create",
                      "dl_server_submit", "dl_server_poll", "dl_server_times",
                      "dl_server_destroy", "dl_problem_get_info", "dl_time_grad_kernel"):
             getattr(L, name).restype = ctypes.c_int

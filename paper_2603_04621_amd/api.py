@@ -173,17 +173,25 @@ class Problem:
         return {k: getattr(i, k) for k, _ in L.ProblemInfo._fields_}
 
     def dual_grad(self, lam, gamma: float, want_x: bool = False, want_eval: bool = False,
-                  stream=None):
-        """(grad [m] fp64 tensor, x [n] or None, dict of scalars or None)."""
+                  stream=None, noalloc: bool = False, out=None):
+        """(grad [m] fp64 tensor, x [n] or None, dict of scalars or None).
+
+        noalloc=True calls dl_dual_grad_noalloc (static library scratch); out
+        may pass preallocated (grad, x) tensors so that the call itself
+        allocates nothing on the device either."""
         import torch
         lam = lam.to(device=self.device, dtype=torch.float64).contiguous()
-        grad = torch.empty(self.m, dtype=torch.float64, device=self.device)
-        x = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_x else None
+        if out is not None:
+            grad, x = out
+        else:
+            grad = torch.empty(self.m, dtype=torch.float64, device=self.device)
+            x = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_x else None
         ev = L.Eval() if want_eval else None
-        L.check(L.lib().dl_dual_grad(self._h, lam.data_ptr(), float(gamma), grad.data_ptr(),
-                                     None if x is None else x.data_ptr(),
-                                     ctypes.byref(ev) if ev is not None else None,
-                                     _stream(stream)), "dl_dual_grad")
+        fn = L.lib().dl_dual_grad_noalloc if noalloc else L.lib().dl_dual_grad
+        L.check(fn(self._h, lam.data_ptr(), float(gamma), grad.data_ptr(),
+                   None if x is None else x.data_ptr(),
+                   ctypes.byref(ev) if ev is not None else None,
+                   _stream(stream)), "dl_dual_grad_noalloc" if noalloc else "dl_dual_grad")
         evd = None if ev is None else {k: getattr(ev, k) for k, _ in L.Eval._fields_}
         return grad, x, evd
 
