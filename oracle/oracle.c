@@ -15,8 +15,10 @@
  *                            the regularizer weighted by v_e^2; v = 1 by default)
  *   Danskin (Section 3.1):  grad g(lam) = A x*(lam) - b,
  *                           x*(lam) = Pi_C(-(A'lam + c)/gamma)  blockwise
- *   simple sets (Section 3.2, Eq.(4),(5)):  per block either the simplex
- *                           {x >= 0, sum x <= 1} or a box {0 <= x <= u}
+ *   simple sets (Section 3.2, Eq.(4),(5)):  per block the simplex
+ *                           {x >= 0, sum x <= 1}, a box {0 <= x <= u}, or the
+ *                           capped simplex {0 <= x <= u, sum x <= 1} (the
+ *                           reading of the "box-cut" set of Section 3.2)
  *   Jacobi row normalization (Section 5): D = diag(1/|A_r*|), A' = D A, b' = D b
  *   gamma continuation (Section 5 "Regularization decay"): gamma decays on a
  *                           schedule and the step cap scales with gamma
@@ -43,6 +45,7 @@
 
 #define ORC_SIMPLEX 0
 #define ORC_BOX 1
+#define ORC_CAPPED 2
 
 #define ORC_OK 0
 #define ORC_EINVAL 1
@@ -60,7 +63,7 @@ typedef struct {
     const double* b;           /* [m]                                         */
     int64_t nblocks;
     const int64_t* block_off;  /* [nblocks+1], contiguous cover of [0, n)     */
-    const uint8_t* block_proj; /* [nblocks], ORC_SIMPLEX or ORC_BOX           */
+    const uint8_t* block_proj; /* [nblocks], ORC_SIMPLEX, ORC_BOX or ORC_CAPPED */
     const double* upper;       /* [n] box bounds, NULL = 1.0                  */
     const double* v;           /* [n] primal scale, NULL = 1.0                */
 } orc_lp;
@@ -83,6 +86,70 @@ static double uu(const orc_lp* lp, int64_t e) { return lp->upper ? lp->upper[e] 
 
 typedef struct { double t, w; } tw_pair;
 
+/* Capped simplex {0 <= x <= u, sum x <= 1}: the reading of the paper's
+ * "box-cut" simple constraint (Section 3.2, "Simple constraints"; Table 1
+ * names it among the projection maps): a box cut by the block's unit
+ * capacity.  KKT gives x_e = clamp(w_e (t_e - tau), 0, u_e) with tau >= 0 and
+ * tau (sum x - 1) = 0.  phi(tau) = sum_e clamp(w_e (t_e - tau), 0, u_e) is
+ * continuous, non-increasing and affine between the breakpoints t_e (where x_e
+ * reaches 0) and t_e - u_e / w_e (where it leaves u_e).  If phi(0) <= 1 then
+ * tau = 0.  Otherwise phi(0) > 1 > 0 = phi(max t): the breakpoints above 0
+ * are sorted, a bisection over them finds consecutive b_k < b_{k+1} with
+ * phi(b_k) >= 1 > phi(b_{k+1}), and tau is the root of the affine piece
+ * between them (breakpoint search, Helgason, Kennington and Lall 1980). */
+static double phi_capped(int64_t d, const double* t, const double* w, const double* u, double tau)
+{
+    double s = 0.0;
+    for (int64_t e = 0; e < d; ++e) {
+        double z = w[e] * (t[e] - tau);
+        double ue = u ? u[e] : 1.0;
+        s += z < 0.0 ? 0.0 : (z > ue ? ue : z);
+    }
+    return s;
+}
+
+static int cmp_dbl_asc(const void* pa, const void* pb)
+{
+    double a = *(const double*)pa, b = *(const double*)pb;
+    return (a > b) - (a < b);
+}
+
+static int project_capped(int64_t d, const double* t, const double* w, const double* u,
+                          double* x, double* tau_out)
+{
+    double tau = 0.0;
+    if (phi_capped(d, t, w, u, 0.0) > 1.0) {
+        double* bp = (double*)malloc(sizeof(double) * (size_t)(2 * d + 1));
+        if (!bp) return ORC_ENOMEM;
+        int64_t nb = 0;
+        bp[nb++] = 0.0;
+        for (int64_t e = 0; e < d; ++e) {
+            double ue = u ? u[e] : 1.0;
+            double lo = t[e] - ue / w[e];
+            if (t[e] > 0.0) bp[nb++] = t[e];
+            if (lo > 0.0) bp[nb++] = lo;
+        }
+        qsort(bp, (size_t)nb, sizeof(double), cmp_dbl_asc);
+        int64_t lo = 0, hi = nb - 1;     /* phi(bp[lo]) >= 1 > phi(bp[hi]) */
+        while (hi - lo > 1) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (phi_capped(d, t, w, u, bp[mid]) >= 1.0) lo = mid;
+            else hi = mid;
+        }
+        double a = bp[lo], b = bp[hi];
+        double fa = phi_capped(d, t, w, u, a), fb = phi_capped(d, t, w, u, b);
+        tau = fa > fb ? a + (fa - 1.0) * (b - a) / (fa - fb) : a;
+        free(bp);
+    }
+    for (int64_t e = 0; e < d; ++e) {
+        double z = w[e] * (t[e] - tau);
+        double ue = u ? u[e] : 1.0;
+        x[e] = z < 0.0 ? 0.0 : (z > ue ? ue : z);
+    }
+    if (tau_out) *tau_out = tau;
+    return ORC_OK;
+}
+
 static int cmp_t_desc(const void* pa, const void* pb)
 {
     double a = ((const tw_pair*)pa)->t, b = ((const tw_pair*)pb)->t;
@@ -102,6 +169,7 @@ int orc_project_block(int proj, int64_t d, const double* t, const double* w,
         if (tau_out) *tau_out = 0.0;
         return ORC_OK;
     }
+    if (proj == ORC_CAPPED) return project_capped(d, t, w, u, x, tau_out);
     if (proj != ORC_SIMPLEX) return ORC_EINVAL;
     double s = 0.0;
     for (int64_t e = 0; e < d; ++e) {

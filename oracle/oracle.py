@@ -21,6 +21,7 @@ SRC_PATH = os.path.join(HERE, "oracle.c")
 
 SIMPLEX = 0
 BOX = 1
+CAPPED = 2
 TRACE_W = 6
 
 

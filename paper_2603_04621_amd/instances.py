@@ -9,8 +9,8 @@ Problem shape (single matching family, Section 3.2 of the paper): sources
 i = 0..I-1 own contiguous blocks of primal variables, one variable per
 eligible (source, destination) edge; each variable has exactly one nonzero
 a_e in row j(e) of A (destination capacity, Eq.(3)); every block carries one
-simple constraint, either the per-source simplex sum_e x_e <= 1, x >= 0
-(Eq.(4),(5)) or a box 0 <= x_e <= u_e.
+simple constraint: the per-source simplex sum_e x_e <= 1, x >= 0
+(Eq.(4),(5)), a box 0 <= x_e <= u_e, or the capped simplex (both).
 
 A is handed over in CSC form with one entry per column, so the column
 pointer is the identity and is not materialised (``Instance.csc`` returns
@@ -52,6 +52,7 @@ import numpy as np
 
 PROJ_SIMPLEX = 0
 PROJ_BOX = 1
+PROJ_CAPPED = 2
 
 SEED_BASE = 4621000
 
@@ -245,7 +246,7 @@ def greedy_capacity(dst, a, block_off, J, seed_key, eps: float = 1e-2) -> np.nda
 
 def _finish(name, seed, I, J, deg, rng, cdf, c_law, a_law, b_frac,
             box_frac=0.0, perm_ids=True, meta=None, seed_key=None,
-            capacity: str = "sum") -> Instance:
+            capacity: str = "sum", capped_frac: float = 0.0) -> Instance:
     deg = np.minimum(deg.astype(np.int64), J)
     if seed_key is None:
         seed_key = [seed, 1]
@@ -266,10 +267,15 @@ def _finish(name, seed, I, J, deg, rng, cdf, c_law, a_law, b_frac,
         b = greedy_capacity(dst, a, block_off, J, list(seed_key) + [2])
     else:
         raise ValueError(f"unknown capacity rule {capacity!r}")
-    if box_frac > 0.0:
-        block_proj = (rng.random(I) < box_frac).astype(np.uint8)
+    if box_frac > 0.0 or capped_frac > 0.0:
+        # one uniform per source: box below box_frac, capped simplex in the
+        # next capped_frac, simplex above; bounds u = U(0.2, 1) on box and
+        # capped blocks
+        r = rng.random(I)
+        block_proj = (r < box_frac).astype(np.uint8)
+        block_proj[(r >= box_frac) & (r < box_frac + capped_frac)] = PROJ_CAPPED
         upper = np.ones(n)
-        is_box = np.repeat(block_proj.astype(bool), deg)
+        is_box = np.repeat(block_proj != PROJ_SIMPLEX, deg)
         upper[is_box] = rng.uniform(0.2, 1.0, size=int(is_box.sum()))
     else:
         block_proj = np.zeros(I, dtype=np.uint8)
@@ -327,13 +333,15 @@ def pareto_degrees(rng, I: int, alpha: float = 1.2, scale: float = 6.5,
 
 
 def heavy(I: int = 2_000_000, J: int = 50_000, seed: int = SEED_BASE + 3,
-          dmax: int = 4096, box_frac: float = 0.3, capacity: str = "sum") -> Instance:
-    """Heavy-tailed blocks with mixed simplex/box projections (2M x 50k full size)."""
+          dmax: int = 4096, box_frac: float = 0.3, capacity: str = "sum",
+          capped_frac: float = 0.0) -> Instance:
+    """Heavy-tailed blocks with mixed simplex/box projections (2M x 50k full size);
+    capped_frac > 0 turns that share of the simplex blocks into capped simplices."""
     rng = np.random.default_rng(seed)
     deg = pareto_degrees(rng, I, dmax=dmax)
     return _finish("heavy", seed, I, J, deg, rng, zipf_cdf(J, 1.1),
                    _neg_lognormal, _lognormal_a, 0.3, box_frac=box_frac,
-                   meta={"I": I, "J": J}, capacity=capacity)
+                   meta={"I": I, "J": J}, capacity=capacity, capped_frac=capped_frac)
 
 
 def batch_sizes(count: int = 256, lo: float = 1e3, hi: float = 1e6,
@@ -381,13 +389,15 @@ def serve_stream(count: int, rate: float = 200.0, lo: float = 1e4, hi: float = 5
 
 
 def random_small(seed: int, I: int, J: int, dmax: int, box_frac: float = 0.5,
-                 zipf: bool = False, b_frac: float = 0.3, capacity: str = "greedy") -> Instance:
+                 zipf: bool = False, b_frac: float = 0.3, capacity: str = "greedy",
+                 capped_frac: float = 0.0) -> Instance:
     """Small mixed instance for property tests (degrees uniform in 1..dmax)."""
     rng = np.random.default_rng(seed)
     deg = rng.integers(1, dmax + 1, size=I)
     cdf = zipf_cdf(J, 1.1) if zipf else uniform_cdf(J)
     return _finish("random_small", seed, I, J, deg, rng, cdf, _neg_lognormal,
-                   _lognormal_a, b_frac, box_frac=box_frac, capacity=capacity)
+                   _lognormal_a, b_frac, box_frac=box_frac, capacity=capacity,
+                   capped_frac=capped_frac)
 
 
 CONFIGS: dict[str, Callable[..., Instance]] = {

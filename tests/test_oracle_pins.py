@@ -111,6 +111,99 @@ def test_projection_special_cases(oracle_lib):
     np.testing.assert_allclose(x, [1.0, 0.0, 0.0])
 
 
+def brute_capped(t, w, u):
+    """min sum (1/(2w)) x^2 - t x over {0 <= x <= u, sum x <= 1}, by
+    enumerating every face: each coordinate at 0, at u or free, with the sum
+    constraint free (free x = w t) or tight (free x = w (t - tau), tau from
+    sum x = 1); keep the feasible candidates, return the least objective."""
+    d = len(t)
+    f = lambda x: np.sum(x * x / (2 * w) - t * x)
+    best, bx = np.inf, None
+    for lab in itertools.product((0, 1, 2), repeat=d):     # 0: at 0, 1: at u, 2: free
+        lab = np.array(lab)
+        F, U = lab == 2, lab == 1
+        for tight in (False, True):
+            x = np.where(U, u, 0.0)
+            if tight:
+                if not F.any():
+                    if abs(x.sum() - 1.0) > 1e-12:
+                        continue
+                else:
+                    tau = (np.sum(w[F] * t[F]) + np.sum(u[U]) - 1.0) / np.sum(w[F])
+                    x[F] = w[F] * (t[F] - tau)
+            else:
+                x[F] = w[F] * t[F]
+            if np.all(x >= -1e-13) and np.all(x <= u + 1e-13) and x.sum() <= 1 + 1e-12:
+                v = f(x)
+                if v < best:
+                    best, bx = v, x
+    return bx
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_capped_projection_matches_face_enumeration(oracle_lib, seed):
+    """The capped simplex (the box-cut reading): breakpoint search against
+    enumeration of all 3^d bound patterns, sum tight or slack.  Draws cover
+    bounds below and above 1, the sum binding or not, ties among t."""
+    O = oracle_lib
+    rng = np.random.default_rng(500 + seed)
+    d = int(rng.integers(1, 7))
+    scale = 10.0 ** rng.uniform(-3, 1)
+    t = rng.normal(size=d) * scale + rng.uniform(-0.5, 1.0) * scale
+    if seed % 5 == 0 and d > 1:
+        t[1] = t[0]
+    w = rng.uniform(0.5, 2.0, size=d) / scale if seed % 2 else np.full(d, 1.0 / scale)
+    u = rng.uniform(0.05, 1.2, size=d)
+    if seed % 7 == 3:
+        u[0] = 0.0
+    x, tau = O.project_block(O.CAPPED, t, w, u)
+    xb = brute_capped(t, w, u)
+    np.testing.assert_allclose(x, xb, rtol=1e-9, atol=1e-12)
+    assert tau >= 0.0
+
+
+def test_capped_projection_reductions(oracle_lib):
+    """Bounds u >= 1 never bind under sum x <= 1: the simplex projection;
+    a box solution summing to at most 1: the box projection; one edge:
+    the clamp to [0, min(u, 1)]."""
+    O = oracle_lib
+    rng = np.random.default_rng(77)
+    for _ in range(20):
+        d = int(rng.integers(1, 30))
+        t = rng.normal(size=d) * 3
+        w = rng.uniform(0.5, 2.0, size=d)
+        xc, tc = O.project_block(O.CAPPED, t, w, 1.0 + rng.uniform(0, 2, size=d))
+        xs, ts = O.project_block(O.SIMPLEX, t, w)
+        np.testing.assert_allclose(xc, xs, rtol=1e-12, atol=1e-14)
+        u = rng.uniform(0.0, 1.0 / d, size=d)
+        xc, tc = O.project_block(O.CAPPED, t, w, u)
+        xb, _ = O.project_block(O.BOX, t, w, u)
+        assert tc == 0.0 and np.array_equal(xc, xb)
+    for t0, u0 in ((-1.0, 0.5), (0.3, 0.5), (3.0, 0.5), (3.0, 2.0), (0.7, 2.0)):
+        x, _ = O.project_block(O.CAPPED, [t0], [1.0], [u0])
+        assert x[0] == pytest.approx(min(max(t0, 0.0), u0, 1.0), rel=1e-15)
+
+
+def capped_kkt_residual(t, w, u, x):
+    """KKT of the capped simplex: x = clamp(w (t - tau), 0, u) for one
+    tau >= 0 with tau (1 - sum x) = 0 and sum x <= 1."""
+    r = max(0.0, float(x.sum()) - 1.0, float(np.max(x - u, initial=0.0)), float(-x.min()))
+    free = (x > 1e-12) & (x < u - 1e-12)
+    if free.any():
+        taus = t[free] - x[free] / w[free]
+        tau = float(np.mean(taus))
+        r = max(r, float(np.max(np.abs(taus - tau))) / max(1.0, abs(tau)))
+    else:
+        # no interior edge: tau is only bracketed (at least t_e of the edges
+        # at 0, and 0 unless the sum is tight); the smallest admissible value
+        # must reproduce x
+        tau = max(0.0, float(np.max(t[x <= 1e-12], initial=0.0))) if x.sum() >= 1 - 1e-12 else 0.0
+    z = np.clip(w * (t - tau), 0.0, u)
+    r = max(r, float(np.max(np.abs(z - x))))
+    r = max(r, -tau / max(1.0, abs(tau)), abs(tau * (1.0 - x.sum())) / max(1.0, abs(tau)))
+    return r
+
+
 def kkt_residual(proj, t, w, u, x):
     """Largest violation of the block's KKT conditions."""
     r = 0.0
@@ -150,13 +243,33 @@ def test_kkt_on_every_block(oracle_lib, seed):
     assert worst < 1e-9
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_kkt_on_every_capped_block(oracle_lib, seed):
+    O = oracle_lib
+    inst = I.random_small(seed, I=300, J=40, dmax=40, box_frac=0.2, capped_frac=0.5)
+    assert np.any(inst.block_proj == I.PROJ_CAPPED)
+    rng = np.random.default_rng(seed)
+    gamma = 10.0 ** rng.uniform(-3, -1)
+    lam = rng.uniform(0, 2, size=inst.m)
+    ev = O.dual_eval(inst, lam, gamma)
+    t = -(inst.c + inst.a * lam[inst.dst])
+    w = np.full(inst.n, 1.0 / gamma)
+    worst = 0.0
+    for i in np.nonzero(inst.block_proj == I.PROJ_CAPPED)[0]:
+        lo, hi = inst.block_off[i], inst.block_off[i + 1]
+        worst = max(worst, capped_kkt_residual(t[lo:hi], w[lo:hi], inst.upper[lo:hi],
+                                               ev.x[lo:hi]))
+    assert worst < 1e-9
+
+
 # ---------------------------------------------------------------------------
 # dual gradient: A'lam, projection, A x (Danskin), dual objective Eq.(2)
 # ---------------------------------------------------------------------------
 
 def test_products_match_dense_algebra(oracle_lib):
     O = oracle_lib
-    inst = I.random_small(3, I=25, J=6, dmax=6, box_frac=0.5)
+    inst = I.random_small(3, I=25, J=6, dmax=6, box_frac=0.3, capped_frac=0.4)
+    assert np.any(inst.block_proj == I.PROJ_CAPPED)
     A = inst.dense()
     rng = np.random.default_rng(0)
     lam = rng.uniform(0, 1, size=inst.m)
@@ -171,6 +284,8 @@ def test_products_match_dense_algebra(oracle_lib):
         w = np.full(hi - lo, 1.0 / gamma)
         if inst.block_proj[i] == I.PROJ_SIMPLEX:
             x[lo:hi] = brute_simplex(t[lo:hi], w)
+        elif inst.block_proj[i] == I.PROJ_CAPPED:
+            x[lo:hi] = brute_capped(t[lo:hi], w, u[lo:hi])
         else:
             x[lo:hi] = brute_box(t[lo:hi], w, u[lo:hi])
     np.testing.assert_allclose(ev.x, x, rtol=1e-9, atol=1e-12)
