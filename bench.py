@@ -1,20 +1,38 @@
 #!/usr/bin/env python3
-"""Benchmark: accelerated dual-ascent iterations per second on the 100M-nnz
-matching LP (I = 10M sources, J = 10k destinations, degree 1+Poisson(9),
-Zipf(1.1) destinations, FP32-stored a and c, FP64 arithmetic and scalars).
+"""Benchmark of the dual-ascent hot path on one MI355X.
 
-One step = one full iteration of the hot path: the fused gradient pass
-(gather, projection, per-destination sums), the FP64 reduction, and the
-ascent step with the gap test every 10 iterations.  Inputs are resident in
-HBM before the timed region.  Prints one JSON line, which also carries the
-roofline of the gradient kernel, the CPU oracle's rate on one host core
-(cpu_baseline) and a multi-core OpenMP implementation's rate on all host
-cores (cpu_parallel_baseline).  --config heavy measures the heavy-tailed
-mixed-projection workload instead; --systems adds batched solves and the
-served stream (with a sweep of lower arrival rates); --ablations adds the
-preconditioning and continuation ablations.
+Headline (`value`): accelerated dual-ascent iterations per second on the
+100M-nnz matching LP (I = 10M sources, J = 10k destinations, degree
+1+Poisson(9), Zipf(1.1) destinations, FP32-stored a and c, FP64 arithmetic
+and scalars) with the paper's greedy-load capacities (Appendix B), under which
+constraints bind and the prices move.  One step = one full iteration of the
+hot path on the hipGraph path dl_solve uses: the fused gradient pass (gather,
+projection, per-destination sums), the FP64 reduction and the ascent step,
+with the gap test every 10 iterations.  Inputs are resident in HBM before the
+timed region; exactly `steps` iterations are timed, after `warmup` untimed
+ones (at least two graph lengths, so the timed solve replays the graph the
+warm-up captured).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--sources I]
+The same JSON line carries:
+  roofline        the fused gradient kernel's algorithmic bytes per launch over
+                  its mean launch time, from a separate pass with HIP events
+                  around every launch on the solve's stream
+  continuation    the 5-stage gamma continuation (1e-1 -> 1e-3) run to
+                  rel_gap 1e-4: iterations, seconds, and the iteration rate of
+                  each stage at the prices that stage sees
+  batched         256 LPs (I log-uniform [1e3, 1e6]) solved to gap 1e-4 in one
+                  batched solve against 256 one-at-a-time solves
+  served          a Poisson stream at 200 req/s (I log-uniform [1e4, 5e6]) to
+                  gap 1e-4 through the server against one-at-a-time solves,
+                  p50/p99 latency
+  heavy           the heavy-tailed mixed-projection workload (2M sources, 50k
+                  destinations, ~60M nnz): kernel rate and roofline, FP32/BF16
+  precision       errors against the FP64 oracle of every storage type on the
+                  headline and the heavy-tailed workloads
+  cpu_baseline    the oracle on one host core (bounded sample)
+  cpu_parallel_baseline  a multi-core OpenMP implementation on all host cores
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-systems] [--no-heavy]
 """
 from __future__ import annotations
 
@@ -24,6 +42,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -31,6 +50,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+METRIC = "dual-ascent iter/s + achieved HBM GB/s at 100M nnz; batched solves/s, p99 lat"
+GAMMA = 1e-3                   # final gamma of every solve here
+GEN_THREADS = 8
 
 
 def log(msg):
@@ -47,7 +69,7 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(workload_key: str):
     """HBM bytes per gradient launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and workload; else None."""
     path = os.path.join(ROOT, "profiles", "grad_kernel_large_counters.json")
     if not os.path.exists(path):
         return None
@@ -58,50 +80,116 @@ def measured_traffic(workload_key: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0, gpu_evals=None):
-    """The FP64 oracle's dual evaluation on this host, single-threaded, on a
-    bounded sample: whole-instance evaluations while the budget lasts (at
-    least one).  With gpu_evals ({storage: (g, grad)} at the same lam), the
-    same oracle evaluations also state each storage's error: against the
-    oracle on the identically rounded data (kernel error) and on the FP64
-    data (storage error)."""
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def continuation_settings(**kw):
+    """gamma 1e-1 -> 1e-3 geometric in 5 stages (a stage ends after 2000
+    iterations or at rel_gap 1e-3), the last stage to rel_gap 1e-4; the step
+    cap is 1/L at each stage (natural preset)."""
+    from paper_2603_04621_amd.api import SolveSettings
+    d = dict(gamma0=1e-1, gamma_final=GAMMA, n_stages=5, stage_iters=2000, stage_tol=1e-3,
+             tol_rel_gap=1e-4, max_iters=20000, check_every=10, preset="natural")
+    d.update(kw)
+    return SolveSettings(**d)
+
+
+def fixed_settings(gamma, iters, check_every=10, **kw):
+    """One stage at gamma, natural steps, the gap never stops it."""
+    from paper_2603_04621_amd.api import SolveSettings
+    return SolveSettings(gamma0=gamma, gamma_final=gamma, max_iters=iters,
+                         check_every=check_every, tol_rel_gap=-1.0, preset="natural", **kw)
+
+
+def graph_rate(p, gamma, steps, warmup, check_every=10, lam0=None):
+    """(lam, outcome, seconds) of exactly `steps` graph-path iterations at
+    gamma, after an untimed warm-up solve that captures the graph."""
+    p.solve(fixed_settings(gamma, max(warmup, 2 * check_every), check_every), lam0=lam0)
+    sync()
+    t0 = time.perf_counter()
+    lam, r = p.solve(fixed_settings(gamma, steps, check_every), lam0=lam0)
+    sync()
+    el = time.perf_counter() - t0
+    assert r.iters == steps, r
+    return lam, r, el
+
+
+def kernel_times(p, gamma, iters, check_every=10, lam0=None):
+    """Mean fused-gradient launch times (ordinary, gap-check) in ms from the
+    eager pass with HIP events around every launch on the solve's stream."""
+    _, r = p.solve(fixed_settings(gamma, iters, check_every, time_kernels=1), lam0=lam0)
+    return r.grad_kernel_ms, r.check_kernel_ms
+
+
+def stage_rate(p, gamma, lam0, iters):
+    """Graph-path iterations/s at gamma from lam0: the difference of two
+    timed solves of 10 and 10 + iters iterations (fixed costs cancel)."""
+    p.solve(fixed_settings(gamma, 20), lam0=lam0)   # captures the graph
+    ts = []
+    for k in (10, 10 + iters):
+        sync()
+        t0 = time.perf_counter()
+        p.solve(fixed_settings(gamma, k), lam0=lam0)
+        sync()
+        ts.append(time.perf_counter() - t0)
+    return iters / max(ts[1] - ts[0], 1e-9)
+
+
+# ----------------------------------------------------------------------------
+# CPU baselines and error statements
+# ----------------------------------------------------------------------------
+
+def grad_errors(inst, ref_inst, ev, g, grad):
+    """(relative error of g, max componentwise gradient error) of a GPU
+    evaluation against an oracle evaluation `ev` on ref_inst's values."""
+    scale = np.bincount(inst.dst, weights=np.abs(ref_inst.a * ev.x), minlength=inst.m) + \
+        np.abs(inst.b)
+    ge = np.abs(grad - ev.grad) / np.maximum(scale, 1e-300)
+    return abs(g - ev.g) / max(1.0, abs(ev.g)), float(ge.max())
+
+
+def precision_statement(inst, lam_np, gamma, gpu_evals, what):
+    """Errors of each storage's GPU evaluation at lam against the oracle on
+    the identically rounded data (kernel error) and on the FP64 data (storage
+    error included)."""
+    from oracle import oracle as O
+    ev64 = O.dual_eval(O.LP.from_instance(inst), lam_np, gamma)
+    out = {"lambda": what, "gamma": gamma,
+           "tolerance": {"grad_componentwise": 1e-5, "g": 1e-6},
+           "oracle_g_fp64_data": ev64.g}
+    for st, (g, grad) in gpu_evals.items():
+        d = {}
+        if st != "f64":
+            ref = inst.rounded(st)
+            evr = O.dual_eval(O.LP.from_instance(ref), lam_np, gamma)
+            d["g_rel_err_same_data"], d["grad_max_rel_err_same_data"] = \
+                grad_errors(inst, ref, evr, g, grad)
+        d["g_rel_err_fp64_data"], d["grad_max_rel_err_fp64_data"] = \
+            grad_errors(inst, inst, ev64, g, grad)
+        out[st] = d
+    return out
+
+
+def cpu_baseline(inst, lam_np, gamma, budget_s: float = 20.0):
+    """The FP64 oracle's dual evaluation on one host core, on a bounded
+    sample: whole-instance evaluations while the budget lasts (1 to 3)."""
     from oracle import oracle as O
     lp = O.LP.from_instance(inst.rounded("f32"))
     t0 = time.perf_counter()
     n = 0
     while True:
-        ev32 = O.dual_eval(lp, lam_np, gamma)
+        O.dual_eval(lp, lam_np, gamma)
         n += 1
         el = time.perf_counter() - t0
         if el >= budget_s or n >= 3 or el * (n + 1) / n > budget_s * 1.5:
             break
     per = el / n
-    out = {"value": 1.0 / per, "unit": "iter/s", "cores": 1, "kind": "oracle",
-           "sample": f"{n} full FP64 dual-gradient evaluation(s) of the same {inst.n}-nnz "
-                     f"instance on one host core ({per:.2f} s each); the O(m) ascent step is "
-                     f"not included"}
-    prec = None
-    if gpu_evals:
-        ev64 = O.dual_eval(O.LP.from_instance(inst), lam_np, gamma)
-
-        def errs(g, grad, ev, ref):
-            scale = np.bincount(inst.dst, weights=np.abs(ref.a * ev.x), minlength=inst.m) + \
-                np.abs(inst.b)
-            ge = np.abs(grad - ev.grad) / np.maximum(scale, 1e-300)
-            return abs(g - ev.g) / max(1.0, abs(ev.g)), float(ge.max())
-
-        prec = {"lambda": "final lambda of the timed FP32 solve", "gamma": gamma,
-                "tolerance": {"grad_componentwise": 1e-5, "g": 1e-6},
-                "oracle_g_fp64_data": ev64.g}
-        for st, (g, grad) in gpu_evals.items():
-            d = {}
-            if st == "f32":
-                # the timed oracle evaluations above ran on the FP32-rounded data
-                d["g_rel_err_same_data"], d["grad_max_rel_err_same_data"] = \
-                    errs(g, grad, ev32, inst.rounded("f32"))
-            d["g_rel_err_fp64_data"], d["grad_max_rel_err_fp64_data"] = errs(g, grad, ev64, inst)
-            prec[st] = d
-    return out, prec
+    return {"value": 1.0 / per, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full FP64 dual-gradient evaluation(s) of the same {inst.n}-nnz "
+                      f"instance on one host core ({per:.2f} s each); the O(m) ascent step is "
+                      f"not included"}
 
 
 def cpu_parallel_baseline(inst, lam_np, gamma, evals: int = 3):
@@ -128,29 +216,191 @@ def cpu_parallel_baseline(inst, lam_np, gamma, evals: int = 3):
                       f"step is not included"}
 
 
-def load_or_generate(I, args):
+# ----------------------------------------------------------------------------
+# instances
+# ----------------------------------------------------------------------------
+
+def make_instance(I, config, sources, dests, cache=None):
+    """The headline (large) or heavy-tailed instance with greedy-load
+    capacities (Appendix B), optionally cached as npy files."""
     fields = ("dst", "a", "c", "b", "block_off", "block_proj", "upper")
-    tag = f"{args.config}_{args.sources}_{args.dests}"
-    seed = I.SEED_BASE + (2 if args.config == "large" else 3)
-    if args.cache:
-        d = os.path.join(args.cache, tag)
+    tag = f"{config}_{sources}_{dests}_greedy"
+    seed = I.SEED_BASE + (2 if config == "large" else 3)
+    if cache:
+        d = os.path.join(cache, tag)
         if all(os.path.exists(os.path.join(d, f + ".npy")) for f in fields[:-1]):
             arr = {f: np.load(os.path.join(d, f + ".npy")) for f in fields
                    if os.path.exists(os.path.join(d, f + ".npy"))}
-            return I.Instance(args.dests, int(arr["dst"].shape[0]), arr["dst"], arr["a"], arr["c"],
+            return I.Instance(dests, int(arr["dst"].shape[0]), arr["dst"], arr["a"], arr["c"],
                               arr["b"], arr["block_off"], arr["block_proj"], arr.get("upper"),
-                              args.config, seed)
-    if args.config == "large":
-        inst = I.large(I=args.sources, J=args.dests)
+                              config + "-greedy", seed, {"capacity": "greedy"})
+    if config == "large":
+        inst = I.large(I=sources, J=dests, capacity="greedy")
     else:
-        inst = I.heavy(I=args.sources, J=args.dests)
-    if args.cache:
-        d = os.path.join(args.cache, tag)
+        inst = I.heavy(I=sources, J=dests, capacity="greedy")
+    if cache:
+        d = os.path.join(cache, tag)
         os.makedirs(d, exist_ok=True)
         for f in fields:
             if getattr(inst, f) is not None:
                 np.save(os.path.join(d, f + ".npy"), getattr(inst, f))
     return inst
+
+
+def generate(fn, items):
+    with ThreadPoolExecutor(GEN_THREADS) as ex:
+        return list(ex.map(fn, items))
+
+
+# ----------------------------------------------------------------------------
+# legs
+# ----------------------------------------------------------------------------
+
+def headline(args, I, Problem):
+    t0 = time.perf_counter()
+    inst = make_instance(I, "large", args.sources, args.dests, args.cache)
+    log(f"large instance with {inst.n} nnz ready in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    prob = Problem(inst, storage=args.storage, autotune=args.autotune)
+    info = prob.info()
+    create_s = time.perf_counter() - t0
+    log(f"created in {create_s:.1f}s: {info}")
+
+    lam, r, el = graph_rate(prob, GAMMA, args.steps, args.warmup)
+    ips = args.steps / el
+    kms, cms = kernel_times(prob, GAMMA, max(args.steps, 100))
+    bytes_per = info["stream_bytes"]
+    log(f"headline: {ips:.1f} iter/s, gradient {kms:.4f} ms, check {cms:.4f} ms")
+
+    # gamma continuation to gap 1e-4: the library's 5-stage solve (second of
+    # two runs: the first captures the graphs), then the stage rates
+    cont = continuation_settings()
+    prob.solve(cont)
+    sync()
+    t0 = time.perf_counter()
+    lam_c, rc = prob.solve(cont)
+    sync()
+    t_gap = time.perf_counter() - t0
+    _, rtr = prob.solve(continuation_settings(trace=True))
+    stage_of = rtr.trace[:, 4].astype(int) if rtr.trace is not None else np.zeros(0, int)
+    gammas = [1e-1 * (GAMMA / 1e-1) ** (s / 4) for s in range(5)]
+    stages = []
+    lam_s = None
+    for s, gs in enumerate(gammas):
+        n_s = int(np.sum(stage_of == s))
+        rate = stage_rate(prob, gs, lam_s, max(args.steps, 100))
+        stages.append({"stage": s, "gamma": gs, "iterations": n_s, "iter_per_s": rate})
+        # the prices at the end of this stage start the next one
+        last = s == 4
+        ss = fixed_settings(gs, 2000 if not last else 20000)
+        ss.tol_rel_gap = 1e-3 if not last else 1e-4
+        lam_s, _ = prob.solve(ss, lam0=lam_s)
+    sync()
+    continuation = {
+        "schedule": "gamma 1e-1 -> 1e-3 geometric, 5 stages; a stage ends at rel_gap 1e-3 or "
+                    "2000 iterations; the last runs to rel_gap 1e-4; step cap 1/L per stage",
+        "converged": bool(rc.converged), "iterations": int(rc.iters), "seconds": t_gap,
+        "final_rel_gap": rc.rel_gap, "final_g": rc.g, "final_gamma": rc.gamma,
+        "stages": stages}
+    log(f"continuation: {continuation}")
+    out = {
+        "value": ips, "ms_per_step": el * 1e3 / args.steps,
+        "config": {"workload": (
+            "matching LP: I=%d sources, J=%d destinations, degree 1+Poisson(9), Zipf(1.1) "
+            "destinations, c=-LogNormal(0,1), a=LogNormal(0,0.5), simplex blocks, greedy-load "
+            "capacities (Appendix B), gamma=1e-3, gap test every 10 iterations"
+            % (args.sources, args.dests)),
+            "nnz": inst.n, "storage": args.storage, "seed": inst.seed},
+        "nnz_per_s": inst.n * ips,
+        "achieved_hbm_gbs": bytes_per / (kms * 1e-3) / 1e9,
+        "stream_gbs": bytes_per * ips / 1e9,
+        "grad_kernel_ms": kms, "check_kernel_ms": cms,
+        "roofline": {"bound": "hbm", "achieved": bytes_per / (kms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_per / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"large-greedy I={args.sources} J={args.dests} "
+                                                 f"{args.storage}"),
+                     "bytes_per_launch": bytes_per,
+                     "kernel": "grad_kernel, ordinary iterations (fused gather + projection + "
+                               "per-destination sums)"},
+        "final_g": r.g, "final_rel_gap": r.rel_gap,
+        "continuation": continuation,
+        "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks", "chunks",
+                                        "lds_rows", "lane_cap", "seg_rmax", "chunks_per_cu",
+                                        "tuned")},
+        "create_seconds": create_s,
+    }
+    # evaluation of every storage type at the converged prices
+    lam_eval = lam_c
+    gpu_evals = {}
+    if not args.no_precision:
+        gg, _, ee = prob.dual_grad(lam_eval, GAMMA, want_eval=True)
+        gpu_evals[args.storage] = (ee["g"], gg.cpu().numpy())
+    prob.close()
+    storages = {}
+    if not args.no_precision:
+        for st in ("bf16", "f64"):
+            if st == args.storage:
+                continue
+            with Problem(inst, storage=st) as ps:
+                _, _, els = graph_rate(ps, GAMMA, args.steps, args.warmup)
+                kms_s, _ = kernel_times(ps, GAMMA, max(args.steps, 100))
+                gs, _, es = ps.dual_grad(lam_eval, GAMMA, want_eval=True)
+                gpu_evals[st] = (es["g"], gs.cpu().numpy())
+                sb = ps.info()["stream_bytes"]
+                storages[st] = {"iter_per_s": args.steps / els, "grad_kernel_ms": kms_s,
+                                "achieved_gbs": sb / (kms_s * 1e-3) / 1e9,
+                                "bytes_per_launch": sb}
+        out["storage_variants"] = storages
+    return out, inst, lam_eval.cpu().numpy(), gpu_evals
+
+
+def heavy_leg(args, I, Problem):
+    """The heavy-tailed workload at full size: kernel rate and roofline for
+    FP32 and BF16 storage, and the error statement of every storage type."""
+    t0 = time.perf_counter()
+    inst = make_instance(I, "heavy", args.heavy_sources, args.heavy_dests, args.cache)
+    log(f"heavy instance with {inst.n} nnz ready in {time.perf_counter() - t0:.1f}s")
+    nbox = int(np.sum(np.repeat(inst.block_proj == I.PROJ_BOX, np.diff(inst.block_off))))
+    out = {"workload": (
+        "matching LP: I=%d sources, J=%d destinations, degree Pareto(1.2, scale 6.5) clipped "
+        "to [1, 4096], Zipf(1.1) destinations, 70%% simplex / 30%% box blocks (u=U(0.2,1)), "
+        "greedy-load capacities, gamma=1e-3" % (args.heavy_sources, args.heavy_dests)),
+        "nnz": inst.n, "nnz_box": nbox}
+    lam = None
+    gpu_evals = {}
+    for st in ("f32", "bf16", "f64"):
+        with Problem(inst, storage=st) as p:
+            info = p.info()
+            if lam is None:
+                # prices of a short solve at the final gamma
+                lam, _ = p.solve(fixed_settings(GAMMA, 200))
+            _, r, el = graph_rate(p, GAMMA, args.steps, args.warmup, lam0=lam)
+            kms, cms = kernel_times(p, GAMMA, max(args.steps, 100), lam0=lam)
+            g, _, e = p.dual_grad(lam, GAMMA, want_eval=True)
+            gpu_evals[st] = (e["g"], g.cpu().numpy())
+            sb = info["stream_bytes"]
+            out[st] = {"iter_per_s": args.steps / el, "grad_kernel_ms": kms,
+                       "check_kernel_ms": cms, "bytes_per_launch": sb,
+                       "achieved_gbs": sb / (kms * 1e-3) / 1e9,
+                       "frac": sb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks",
+                                                       "chunks", "lds_rows")}}
+            log(f"heavy {st}: {out[st]}")
+    if not args.no_precision:
+        out["precision"] = precision_statement(inst, lam.cpu().numpy(), GAMMA, gpu_evals,
+                                               "prices after 200 iterations at gamma = 1e-3")
+    return out
+
+
+def fcfs_latencies(arrivals, service):
+    """Latencies of one-at-a-time service in arrival order."""
+    done_prev, out = 0.0, []
+    for ta, sv in zip(arrivals, service):
+        begin = max(ta, done_prev)
+        done_prev = begin + sv
+        out.append(done_prev - ta)
+    return np.array(out), done_prev
 
 
 def serve_stream_run(reqs, arrivals, st, slots):
@@ -192,97 +442,83 @@ def serve_stream_run(reqs, arrivals, st, slots):
     return t_srv, np.array(lat), res
 
 
-def fcfs_latencies(arrivals, service):
-    """Latencies of one-at-a-time service in arrival order."""
-    done_prev, out = 0.0, []
-    for ta, sv in zip(arrivals, service):
-        begin = max(ta, done_prev)
-        done_prev = begin + sv
-        out.append(done_prev - ta)
-    return np.array(out), done_prev
-
-
-def systems(args, log):
-    """Batched and served solves against one-at-a-time plain solves, all to
-    rel_gap 1e-4 with the same gamma continuation (binding capacities)."""
-    import threading
-    import torch
-    from paper_2603_04621_amd import instances as I
-    from paper_2603_04621_amd.api import Problem, Server, SolveSettings, batch_solve
-
-    st = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=5, stage_iters=2000,
-                       stage_tol=1e-3, tol_rel_gap=1e-4, max_iters=20000, check_every=10,
-                       max_step=1e-1, init_step=1e-3)
-    out = {}
-    # ---- batched: the 256-LP workload (I log-uniform [1e3, hi])
+def batched_leg(args, I, Problem, batch_solve):
+    st = continuation_settings()
     sizes = I.batch_sizes(args.batch_count, 1e3, args.batch_hi)
     t0 = time.perf_counter()
-    insts = [I.batch_member(int(n), k, capacity="greedy") for k, n in enumerate(sizes)]
-    log(f"batch: {len(insts)} LPs, {sum(x.n for x in insts)} nnz generated in "
-        f"{time.perf_counter() - t0:.1f}s")
+    insts = generate(lambda kn: I.batch_member(int(kn[1]), kn[0], capacity="greedy"),
+                     list(enumerate(sizes)))
+    nnz = int(sum(x.n for x in insts))
+    log(f"batch: {len(insts)} LPs, {nnz} nnz generated in {time.perf_counter() - t0:.1f}s")
     probs = [Problem(x) for x in insts]
-    torch.cuda.synchronize()
+    sync()
     t0 = time.perf_counter()
     seq = [p.solve(st)[1] for p in probs]
-    torch.cuda.synchronize()
+    sync()
     t_seq = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, bat = batch_solve(probs, st)
-    torch.cuda.synchronize()
+    sync()
     t_bat = time.perf_counter() - t0
     for p in probs:
         p.close()
-    out["batched"] = {
+    out = {
         "workload": f"{len(insts)} matching LPs, I log-uniform [1e3, {args.batch_hi:.0e}], "
                     f"J = I/200, degree 1+Poisson(9), Zipf(1.1), greedy-load capacities, "
                     f"gamma 1e-1 -> 1e-3 in 5 stages, to rel_gap 1e-4",
-        "nnz_total": int(sum(x.n for x in insts)),
+        "nnz_total": nnz,
         "solves_per_s": len(insts) / t_bat, "seconds": t_bat,
         "sequential_solves_per_s": len(insts) / t_seq, "sequential_seconds": t_seq,
         "speedup": t_seq / t_bat,
         "converged": int(sum(r.converged for r in bat)),
         "sequential_converged": int(sum(r.converged for r in seq)),
         "max_rel_gap": float(max(r.rel_gap for r in bat)),
+        "sequential_max_rel_gap": float(max(r.rel_gap for r in seq)),
         "iters_max": int(max(r.iters for r in bat)),
     }
-    log(f"batched: {out['batched']}")
-    # ---- served: Poisson stream
+    log(f"batched: {out}")
+    return out
+
+
+def served_leg(args, I, Problem):
+    st = continuation_settings()
     arr = I.serve_stream(args.serve_count, rate=args.serve_rate, lo=1e4, hi=args.serve_hi)
     t0 = time.perf_counter()
-    reqs = [I.serve_member(n, k, capacity="greedy") for k, (_, n) in enumerate(arr)]
-    log(f"serve: {len(reqs)} requests, {sum(x.n for x in reqs)} nnz generated in "
-        f"{time.perf_counter() - t0:.1f}s")
+    reqs = generate(lambda kv: I.serve_member(kv[1][1], kv[0], capacity="greedy"),
+                    list(enumerate(arr)))
+    nnz = int(sum(x.n for x in reqs))
+    log(f"serve: {len(reqs)} requests, {nnz} nnz generated in {time.perf_counter() - t0:.1f}s")
     t_srv, lat, res = serve_stream_run(reqs, [ta for ta, _ in arr], st, args.serve_slots)
     # one-at-a-time baseline: measured create + solve per request, first come
     # first served on the same arrival times
     svc = []
     for x in reqs:
-        torch.cuda.synchronize()
+        sync()
         t1 = time.perf_counter()
         with Problem(x) as p:
             p.solve(st)
-        torch.cuda.synchronize()
+        sync()
         svc.append(time.perf_counter() - t1)
     seq_lat, done_prev = fcfs_latencies([ta for ta, _ in arr], svc)
-    out["served"] = {
+    out = {
         "workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate:g}/s, "
-                    f"I log-uniform [1e4, {args.serve_hi:.0e}], J = I/500, 70/30 simplex/box, "
-                    f"greedy-load capacities, to rel_gap 1e-4; {args.serve_slots} slots, "
-                    f"200 GB budget",
+                    f"I log-uniform [1e4, {args.serve_hi:.0e}], J = I/500, degree 1+Poisson(9), "
+                    f"70/30 simplex/box, greedy-load capacities, to rel_gap 1e-4; "
+                    f"{args.serve_slots} slots, 200 GB budget; requests generated on the host "
+                    f"before the stream starts",
+        "nnz_total": nnz,
         "solves_per_s": len(reqs) / t_srv,
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
-        # admission (queue + build) and on-device time of the served requests
         "p50_admission_s": float(np.percentile([r[2][1] - r[2][0] for r in res], 50)),
         "p50_on_device_s": float(np.percentile([r[2][2] - r[2][1] for r in res], 50)),
         "sequential_solves_per_s": len(reqs) / done_prev,
         "sequential_p50_latency_s": float(np.percentile(seq_lat, 50)),
         "sequential_p99_latency_s": float(np.percentile(seq_lat, 99)),
         "converged": int(sum(r[0].converged for r in res)),
+        "max_rel_gap": float(max(r[0].rel_gap for r in res)),
     }
-    log(f"served: {out['served']}")
-    # below saturation: the same requests with their arrival times stretched
-    # to lower rates
+    log(f"served: {out}")
     sweep = []
     for rate in [float(x) for x in args.serve_sweep.split(",") if x]:
         arr_r = [ta * args.serve_rate / rate for ta, _ in arr]
@@ -296,24 +532,21 @@ def systems(args, log):
                       "sequential_p99_latency_s": float(np.percentile(sl, 99)),
                       "converged": int(sum(r[0].converged for r in res_r))})
         log(f"served at {rate:g}/s: {sweep[-1]}")
-    out["served"]["rate_sweep"] = sweep
+    if sweep:
+        out["rate_sweep"] = sweep
     return out
 
 
-def ablations(args, log):
+def ablations(args, I, Problem):
     """Section 7's ablations on a binding matching LP (greedy-load capacities,
     Appendix B): iterations and time to rel_gap 1e-4 at gamma = 1e-3 with and
     without Jacobi row normalization, with gamma continuation (geometric, 5
     stages from 1e-1) and with gamma fixed, and the paper's own schedule
     (0.16 -> 0.01 halved every 25 iterations).  The step cap is the safe 1/L
-    in every run: gamma after normalization (|A'|^2 = 1), gamma / max_j
-    |A_j|^2 without it."""
-    import torch
-    from paper_2603_04621_amd import instances as I
-    from paper_2603_04621_amd.api import Problem, SolveSettings
+    in every run (natural preset on each problem's own |A'|^2)."""
+    from paper_2603_04621_amd.api import SolveSettings
     inst = I.large(I=args.ablation_sources, J=max(2, args.ablation_sources // 500),
                    capacity="greedy")
-    rn2 = float(np.bincount(inst.dst, weights=inst.a ** 2, minlength=inst.m).max())
     runs = []
     cases = [("jacobi+continuation", True, 1e-1, 1e-3, 5, 2000, 1e-3),
              ("none+continuation", False, 1e-1, 1e-3, 5, 2000, 1e-3),
@@ -321,15 +554,14 @@ def ablations(args, log):
              ("none+fixed", False, 1e-3, 1e-3, 1, 0, 0.0),
              ("jacobi+paper-schedule", True, 0.16, 0.01, 5, 25, 0.0)]
     for name, rnorm, g0, g1, ns, siters, stol in cases:
-        scale = 1.0 if rnorm else 1.0 / rn2
         s = SolveSettings(gamma0=g0, gamma_final=g1, n_stages=ns, stage_iters=siters,
                           stage_tol=stol, tol_rel_gap=1e-4, max_iters=args.ablation_iters,
-                          check_every=10, max_step=g0 * scale, init_step=1e-2 * g0 * scale)
+                          check_every=10, preset="natural")
         with Problem(inst, storage="f32", row_normalize=rnorm) as p:
-            torch.cuda.synchronize()
+            sync()
             t0 = time.perf_counter()
             _, r = p.solve(s)
-            torch.cuda.synchronize()
+            sync()
             el = time.perf_counter() - t0
         runs.append({"case": name, "converged": bool(r.converged), "iterations": int(r.iters),
                      "seconds": el, "final_gamma": r.gamma, "rel_gap": r.rel_gap, "g": r.g})
@@ -346,44 +578,37 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--config", default="large", choices=["large", "heavy"],
-                    help="large: 10M sources, 10k destinations, Poisson degrees (the headline); "
-                         "heavy: 2M sources, 50k destinations, Pareto degrees, 30%% box blocks")
-    ap.add_argument("--sources", type=int, default=None)
-    ap.add_argument("--dests", type=int, default=None)
+    ap.add_argument("--sources", type=int, default=10_000_000)
+    ap.add_argument("--dests", type=int, default=10_000)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--heavy-sources", type=int, default=2_000_000)
+    ap.add_argument("--heavy-dests", type=int, default=50_000)
+    ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tailed leg")
+    ap.add_argument("--no-systems", action="store_true",
+                    help="skip the batched and served legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-binding", action="store_true",
-                    help="skip the binding-capacity variant")
-    ap.add_argument("--systems", action="store_true",
-                    help="also measure batched and served solves")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16 / FP64 storage runs and the error statements")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-hi", type=float, default=1e6)
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-hi", type=float, default=5e5)
+    ap.add_argument("--serve-hi", type=float, default=5e6)
     ap.add_argument("--serve-slots", type=int, default=32)
-    ap.add_argument("--serve-sweep", default="25,50,100",
-                    help="lower arrival rates (req/s) re-run with the same requests; empty: none")
+    ap.add_argument("--serve-sweep", default="",
+                    help="lower arrival rates (req/s) re-run with the same requests")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--ablations", action="store_true",
                     help="also run the preconditioning / continuation ablations")
     ap.add_argument("--ablation-sources", type=int, default=1_000_000)
     ap.add_argument("--ablation-iters", type=int, default=20000)
-    ap.add_argument("--no-precision", action="store_true",
-                    help="skip the BF16 / FP64 storage runs and the error statement")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the work layout by timing candidates on a sample at create")
     ap.add_argument("--cache", default=None,
-                    help="directory to save/load the generated instance (npy files)")
+                    help="directory to save/load the generated instances (npy files)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
-    if args.sources is None:
-        args.sources = 10_000_000 if args.config == "large" else 2_000_000
-    if args.dests is None:
-        args.dests = 10_000 if args.config == "large" else 50_000
     if args.copy_calibration:
         import torch
         torch.cuda.set_device(0)
@@ -402,142 +627,34 @@ def main():
 
     import torch
     from paper_2603_04621_amd import instances as I
-    from paper_2603_04621_amd.api import Problem, SolveSettings
+    from paper_2603_04621_amd.api import Problem, batch_solve
 
     torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    inst = load_or_generate(I, args)
-    log(f"instance with {inst.n} nnz ready in {time.perf_counter() - t0:.1f}s")
-    t0 = time.perf_counter()
-    prob = Problem(inst, storage=args.storage, autotune=args.autotune)
-    info = prob.info()
-    create_s = time.perf_counter() - t0
-    log(f"created in {create_s:.1f}s: {info}")
-
-    gamma = 1e-3
-    # the solve the steps belong to: one gamma stage at the final gamma, the
-    # paper's step-size ratio, gap test every check_every iterations; the gap
-    # never stops it (negative tolerance) so exactly `steps` iterations run
-    def settings(iters):
-        return SolveSettings(gamma0=gamma, gamma_final=gamma, max_iters=iters,
-                             check_every=args.check_every, tol_rel_gap=-1.0, max_step=gamma,
-                             init_step=1e-2 * gamma, time_kernels=1)
-
-    def timed(p):
-        p.solve(settings(args.warmup))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lam, r = p.solve(settings(args.steps))
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        assert r.iters == args.steps, r
-        return lam, r, el
-
-    lam, r, el = timed(prob)
-    # the other storage types at the same lambda (errors stated against the
-    # oracle in the CPU-baseline leg) and their iteration rate
-    gpu_evals = {}
-    if not args.no_precision:
-        g32, _, e32 = prob.dual_grad(lam, gamma, want_eval=True)
-        gpu_evals[args.storage] = (e32["g"], g32.cpu().numpy())
-    ms = el * 1e3 / args.steps
-    ips = args.steps / el
-    bytes_per = info["stream_bytes"]
-    achieved = bytes_per / (r.grad_kernel_ms * 1e-3) / 1e9
-    wl = f"{args.config} I={args.sources} J={args.dests} {args.storage}"
-    traffic = measured_traffic(wl)
-    if args.config == "large":
-        metric = "dual-ascent iter/s at 100M nnz (matching LP, FP32-stored a and c)"
-        workload = ("matching LP: I=%d sources, J=%d destinations, degree 1+Poisson(9), Zipf(1.1) "
-                    "destinations, simplex blocks, gamma=1e-3, gap test every %d iterations" %
-                    (args.sources, args.dests, args.check_every))
-    else:
-        metric = "dual-ascent iter/s, heavy-tailed blocks with mixed projections"
-        workload = ("matching LP: I=%d sources, J=%d destinations, degree Pareto(1.2, scale 6.5) "
-                    "clipped to [1, 4096], Zipf(1.1) destinations, 70%% simplex / 30%% box blocks, "
-                    "gamma=1e-3, gap test every %d iterations" %
-                    (args.sources, args.dests, args.check_every))
-    out = {
-        "metric": metric,
-        "value": ips,
-        "unit": "iter/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": workload, "nnz": inst.n, "storage": args.storage,
-                   "seed": inst.seed},
-        "nnz_per_s": inst.n * ips,
-        "stream_gbs": bytes_per * ips / 1e9,
-        "grad_kernel_ms": r.grad_kernel_ms,
-        "check_kernel_ms": r.check_kernel_ms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": bytes_per,
-                     "kernel": "grad_kernel, ordinary iterations (fused gather + projection + per-destination sums)"},
-        "final_g": r.g,
-        "final_rel_gap": r.rel_gap,
-        "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks", "chunks",
-                                        "lds_rows", "lane_cap", "seg_rmax", "chunks_per_cu",
-                                        "tuned")},
-        "create_seconds": create_s,
-    }
-    if not args.no_binding:
-        # same sparsity and values with the paper's greedy-load capacities
-        # (Appendix B), under which constraints bind and the prices move
-        lam_b = I.greedy_capacity(inst.dst, inst.a, inst.block_off, inst.m,
-                                  [inst.seed, 1, 2])
-        inst_b = I.Instance(inst.m, inst.n, inst.dst, inst.a, inst.c, lam_b, inst.block_off,
-                            inst.block_proj, inst.upper, args.config + "-binding", inst.seed)
-        prob.close()
-        with Problem(inst_b, storage=args.storage, autotune=args.autotune) as pb:
-            _, rb, elb = timed(pb)
-        out["binding_variant"] = {
-            "capacity": "greedy load (Appendix B)", "iter_per_s": args.steps / elb,
-            "grad_kernel_ms": rb.grad_kernel_ms,
-            "check_kernel_ms": rb.check_kernel_ms,
-            "achieved_gbs": bytes_per / (rb.grad_kernel_ms * 1e-3) / 1e9,
-            "final_rel_gap": rb.rel_gap}
-    lam_np = lam.cpu().numpy()
-    prob.close()
-    storages = {}
-    if not args.no_precision:
-        for st in ("bf16", "f64"):
-            if st == args.storage:
-                continue
-            with Problem(inst, storage=st) as ps:
-                p_steps = max(1, min(args.steps, 300))
-                ps.solve(settings(min(args.warmup, 20)))
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, rs = ps.solve(settings(p_steps))
-                torch.cuda.synchronize()
-                els = time.perf_counter() - t0
-                gs, _, es = ps.dual_grad(lam, gamma, want_eval=True)
-                gpu_evals[st] = (es["g"], gs.cpu().numpy())
-                sb = ps.info()["stream_bytes"]
-                storages[st] = {"iter_per_s": p_steps / els, "steps": p_steps,
-                                "grad_kernel_ms": rs.grad_kernel_ms,
-                                "achieved_gbs": sb / (rs.grad_kernel_ms * 1e-3) / 1e9,
-                                "bytes_per_launch": sb}
-        out["storage_variants"] = storages
-    if args.systems:
-        out.update(systems(args, log))
+    head, inst, lam_np, gpu_evals = headline(args, I, Problem)
+    out = {"metric": METRIC, "value": head.pop("value"), "unit": "iter/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": head.pop("ms_per_step"), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    out.update(head)
+    if not args.no_systems:
+        out["batched"] = batched_leg(args, I, Problem, batch_solve)
+        out["batched_solves_per_s"] = out["batched"]["solves_per_s"]
+        out["served"] = served_leg(args, I, Problem)
+        out["served_solves_per_s"] = out["served"]["solves_per_s"]
+        out["served_p99_latency_s"] = out["served"]["p99_latency_s"]
+    if not args.no_heavy:
+        out["heavy"] = heavy_leg(args, I, Problem)
     if args.ablations:
-        out["ablations"] = ablations(args, log)
+        out["ablations"] = ablations(args, I, Problem)
+    if not args.no_precision and gpu_evals:
+        log("error statement against the oracle")
+        out["precision"] = precision_statement(inst, lam_np, GAMMA, gpu_evals,
+                                               "final prices of the continuation solve")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        out["cpu_baseline"], prec = cpu_baseline(inst, lam_np, gamma, args.cpu_budget,
-                                                 gpu_evals if gpu_evals else None)
-        if prec is not None:
-            out["precision"] = prec
+        out["cpu_baseline"] = cpu_baseline(inst, lam_np, GAMMA, args.cpu_budget)
         log("timing the multi-core CPU baseline")
-        out["cpu_parallel_baseline"] = cpu_parallel_baseline(inst, lam_np, gamma)
+        out["cpu_parallel_baseline"] = cpu_parallel_baseline(inst, lam_np, GAMMA)
     print(json.dumps(out), flush=True)
 
 

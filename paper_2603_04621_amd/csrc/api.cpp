@@ -412,6 +412,10 @@ static dl_status dalloc(dl_problem* p, T** ptr, size_t count, const char* what)
 static void free_problem(dl_problem* p)
 {
     if (!p) return;
+    if (p->gc.exec) (void)hipGraphExecDestroy(p->gc.exec);
+    if (p->gc.graph) (void)hipGraphDestroy(p->gc.graph);
+    for (auto e : p->gc.ev)
+        if (e) (void)hipEventDestroy(e);
     for (void* q : p->allocs) (void)hipFree(q);
     if (p->st_host) (void)hipHostFree(p->st_host);
     delete p;

@@ -75,6 +75,7 @@ struct SolveState {
     double g, P, rel_gap, max_infeas, gnorm, obj;
     double gamma_eval;       // gamma of the last evaluation
     int64_t k, ks;
+    int64_t kmax;            // iteration cap of the solve (set at init)
     int32_t stage, done, converged, status;
     int32_t stage_eval, pad;
     // the step the scalar kernel chose for the row kernel

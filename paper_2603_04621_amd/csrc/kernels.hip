@@ -280,9 +280,10 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
     __shared__ double v[9];
     // thread 0 reads the state before the reductions, so its loads overlap them
     double cur_gamma = 0.0, cur_eta = 0.0, cur_eta_cap = 0.0, cur_tm = 0.0;
-    int64_t cur_k = 0, cur_ks = 0;
+    int64_t cur_k = 0, cur_ks = 0, cur_kmax = 0;
     int32_t cur_stage = 0;
     if (threadIdx.x == 0) {
+        cur_kmax = st->kmax;
         cur_gamma = st->gamma;
         cur_eta = st->eta;
         cur_eta_cap = st->eta_cap;
@@ -366,7 +367,7 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
                     st->ks = ks + 1;
                 }
                 st->k = k + 1;
-                if (k + 1 >= P.max_iters) st->done = 1;
+                if (k + 1 >= cur_kmax) st->done = 1;
             }
         }
         sc[0] = eta;
@@ -539,6 +540,7 @@ __global__ void solve_init_kernel(SolveState* st, SolveParams prm, const double*
         st->stage_eval = 0;
         st->k = 0;
         st->ks = 0;
+        st->kmax = prm.max_iters;
         st->stage = 0;
         st->done = prm.max_iters <= 0 ? 1 : 0;
         st->converged = 0;

@@ -48,6 +48,15 @@ struct dl_problem {
     dl::SolveState* st = nullptr;
     dl::SolveState* st_host = nullptr;   // pinned mirror (2 slots)
     std::vector<void*> allocs;
+    // the last solve's graph of `seg` iterations, replayed by later solves
+    // with the same parameters (no trace); freed with the problem
+    struct {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        int64_t seg = 0, check_every = 0;
+        dl::SolveParams prm;
+    } gc;
 };
 
 namespace dlh {

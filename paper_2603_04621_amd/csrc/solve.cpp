@@ -109,30 +109,57 @@ extern "C" dl_status dl_solve(dl_problem* p, const dl_solve_opts* o, double* lam
         bool stop = false;
         const int64_t nfull = N / seg;
         if (nfull > 0) {
-            TRY(hipStreamCreateWithFlags(&cl.cap, hipStreamNonBlocking), "capture stream");
-            TRY(hipStreamBeginCapture(cl.cap, hipStreamCaptureModeThreadLocal), "begin capture");
-            for (int64_t q = 0; q < seg; ++q) {
-                const int check = o->check_every > 0 && (q + 1) % o->check_every == 0;
-                hipError_t e = dlh::enqueue_iteration(p, prm, check, cl.trace, cl.cap, nullptr, nullptr);
-                if (e != hipSuccess) {
-                    hipGraph_t gtmp = nullptr;
-                    (void)hipStreamEndCapture(cl.cap, &gtmp);
-                    if (gtmp) (void)hipGraphDestroy(gtmp);
-                    return hip_fail(e, "capture iteration");
+            // a graph of `seg` iterations: the problem's cached one when the
+            // last solve captured it with the same parameters, else a new
+            // capture (kept for the next solve unless it records a trace)
+            // (the iteration cap is read from the device state, so solves of
+            // different lengths share a graph)
+            auto& gc = p->gc;
+            SolveParams key = prm;
+            key.max_iters = 0;
+            const bool same = gc.exec && !cl.trace && gc.seg == seg && gc.check_every == o->check_every &&
+                              std::memcmp(&gc.prm, &key, sizeof key) == 0;
+            hipGraphExec_t exec = same ? gc.exec : nullptr;
+            if (!exec) {
+                TRY(hipStreamCreateWithFlags(&cl.cap, hipStreamNonBlocking), "capture stream");
+                TRY(hipStreamBeginCapture(cl.cap, hipStreamCaptureModeThreadLocal), "begin capture");
+                for (int64_t q = 0; q < seg; ++q) {
+                    const int check = o->check_every > 0 && (q + 1) % o->check_every == 0;
+                    hipError_t e = dlh::enqueue_iteration(p, prm, check, cl.trace, cl.cap, nullptr, nullptr);
+                    if (e != hipSuccess) {
+                        hipGraph_t gtmp = nullptr;
+                        (void)hipStreamEndCapture(cl.cap, &gtmp);
+                        if (gtmp) (void)hipGraphDestroy(gtmp);
+                        return hip_fail(e, "capture iteration");
+                    }
+                }
+                TRY(hipStreamEndCapture(cl.cap, &cl.graph), "end capture");
+                TRY(hipGraphInstantiate(&cl.exec, cl.graph, nullptr, nullptr, 0), "instantiate graph");
+                exec = cl.exec;
+                if (!cl.trace) {
+                    // hand the new graph to the problem (the old one is idle:
+                    // solves on one problem do not overlap)
+                    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+                    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+                    gc.exec = cl.exec;
+                    gc.graph = cl.graph;
+                    cl.exec = nullptr;
+                    cl.graph = nullptr;
+                    gc.seg = seg;
+                    gc.check_every = o->check_every;
+                    gc.prm = key;
                 }
             }
-            TRY(hipStreamEndCapture(cl.cap, &cl.graph), "end capture");
-            TRY(hipGraphInstantiate(&cl.exec, cl.graph, nullptr, nullptr, 0), "instantiate graph");
-            cl.events.resize(2, nullptr);
-            for (auto& e : cl.events) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+            for (auto& e : gc.ev)
+                if (!e) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
             for (int64_t gi = 0; gi < nfull && !stop; ++gi) {
-                TRY(hipGraphLaunch(cl.exec, s), "graph launch");
+                TRY(hipGraphLaunch(exec, s), "graph launch");
                 k += seg;
                 const int slot = (int)(gi & 1);
                 TRY(hipMemcpyAsync(hst + slot, p->st, sizeof(SolveState), hipMemcpyDeviceToHost, s), "copy state");
-                TRY(hipEventRecord(cl.events[slot], s), "record");
+                TRY(hipEventRecord(gc.ev[slot], s), "record");
                 if (gi >= 1) {
-                    TRY(hipEventSynchronize(cl.events[1 - slot]), "poll");
+                    TRY(hipEventSynchronize(gc.ev[1 - slot]), "poll");
                     if (hst[1 - slot].done) stop = true;
                 }
             }
