@@ -11,7 +11,8 @@
  * every column of A holds at most one nonzero (one matching family,
  * A = [D_1 ... D_I] with diagonal D_i), and the columns are grouped into
  * contiguous blocks, one per source, each carrying one simple constraint:
- * the simplex {x >= 0, sum x <= 1} (Eq.(4),(5)) or a box {0 <= x <= u}.
+ * the simplex {x >= 0, sum x <= 1} (Eq.(4),(5)), a box {0 <= x <= u} or
+ * both at once (dl_proj).
  * By Danskin's theorem grad g(lam) = A x*(lam) - b with
  * x*(lam) = Pi_C(-(A'lam + c)/gamma) blockwise (Section 3.1).
  *
@@ -55,7 +56,14 @@ typedef enum {
     DL_ERR_NOT_FOUND = 8       /* unknown server ticket                          */
 } dl_status;
 
-typedef enum { DL_PROJ_SIMPLEX = 0, DL_PROJ_BOX = 1 } dl_proj;
+/* Simple constraint of a block (Section 3.2, "Simple constraints"):
+ *   DL_PROJ_SIMPLEX  {x >= 0, sum x <= 1}                    (Eq.(4),(5))
+ *   DL_PROJ_BOX      {0 <= x <= u}
+ *   DL_PROJ_CAPPED   {0 <= x <= u, sum x <= 1}: the box cut by the block's
+ *                    unit capacity, this library's reading of the paper's
+ *                    "box-cut" set (a capacity k other than 1 is the same
+ *                    set after scaling the block's columns by k).          */
+typedef enum { DL_PROJ_SIMPLEX = 0, DL_PROJ_BOX = 1, DL_PROJ_CAPPED = 2 } dl_proj;
 typedef enum { DL_CSC = 0, DL_CSR = 1 } dl_layout;
 /* Storage of the per-nonzero values a and c on the device.  Arithmetic is
  * FP64 in every case; the choice only sets the bytes streamed per iteration. */
@@ -72,7 +80,7 @@ typedef struct dl_server dl_server;
  *   val[nnz] entries of A; c[n] costs; b[m] capacities.
  *   block_off[num_blocks+1] tiles [0, n) contiguously (block_off[0] = 0,
  *           non-decreasing, block_off[num_blocks] = n); block_proj[num_blocks]
- *           holds dl_proj values; upper[n] box bounds (NULL = 1.0; ignored on
+ *           holds dl_proj values; upper[n] bounds u (NULL = 1.0; ignored on
  *           simplex blocks).
  * Requirements: indices in range, values finite, at most one entry per column
  * (several families are DL_ERR_UNSUPPORTED), upper >= 0, m >= 1.

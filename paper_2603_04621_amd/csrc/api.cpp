@@ -152,7 +152,7 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
     }
     for (int64_t i = 0; i < d->num_blocks; ++i) {
         if (d->block_off[i + 1] < d->block_off[i]) { set_error("block_off decreases at %lld", (long long)i); return DL_ERR_INVALID_ARG; }
-        if (d->block_proj[i] > 1) { set_error("block_proj[%lld] = %d is not a dl_proj", (long long)i, (int)d->block_proj[i]); return DL_ERR_INVALID_ARG; }
+        if (d->block_proj[i] > DL_PROJ_CAPPED) { set_error("block_proj[%lld] = %d is not a dl_proj", (long long)i, (int)d->block_proj[i]); return DL_ERR_INVALID_ARG; }
         if (d->block_off[i + 1] - d->block_off[i] >= (int64_t)1 << 31) { set_error("block too large"); return DL_ERR_UNSUPPORTED; }
     }
     if (!finite_all(d->val, d->nnz)) { set_error("val has a non-finite entry"); return DL_ERR_INVALID_ARG; }
@@ -269,9 +269,10 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
     const int64_t I = d->num_blocks;
     const int64_t dmax_lane = std::max<int64_t>(cap, 64 * (int64_t)rmax);
     // buckets: [lg / 2][proj][degree] for LANE items, then WG blocks by proj
-    std::vector<std::vector<int64_t>> lane((size_t)4 * 2 * (dmax_lane + 1));
+    constexpr int NPJ = 3;   // projection types (dl_proj)
+    std::vector<std::vector<int64_t>> lane((size_t)4 * NPJ * (dmax_lane + 1));
     auto bucket = [&](int lg, int pr, int64_t deg) -> std::vector<int64_t>& {
-        return lane[((size_t)(lg / 2) * 2 + pr) * (dmax_lane + 1) + deg];
+        return lane[((size_t)(lg / 2) * NPJ + pr) * (dmax_lane + 1) + deg];
     };
     std::vector<std::pair<int64_t, int64_t>> wgb;   // (proj, block)
     for (int64_t i = 0; i < I; ++i) {
@@ -298,7 +299,7 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
     std::vector<Proto> kinds[2];
     std::vector<int64_t> gb;
     for (int lg = 0; lg <= 6; lg += 2)
-        for (int pr = 0; pr < 2; ++pr)
+        for (int pr = 0; pr < NPJ; ++pr)
             for (int64_t deg = 1; deg <= dmax_lane; ++deg) {
                 const auto& v = bucket(lg, pr, deg);
                 const size_t per = (size_t)64 >> lg;
@@ -496,7 +497,8 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         for (int64_t j = 0; j < m; ++j) mx = std::max(mx, opts.row_normalize ? (r2[j] > 0.0 ? 1.0 : 0.0) : r2[j]);
         p->anorm2 = mx > 0.0 ? mx : 1.0;
     }
-    for (int64_t i = 0; i < d->num_blocks && !p->has_box; ++i) p->has_box = d->block_proj[i] == DL_PROJ_BOX;
+    // per-edge bounds are stored when any block has them (box and capped)
+    for (int64_t i = 0; i < d->num_blocks && !p->has_box; ++i) p->has_box = d->block_proj[i] != DL_PROJ_SIMPLEX;
 
     // work items and chunks
     const int cus = device_cus(p->device);
@@ -535,7 +537,7 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         if (p->has_box) {
             ebox.assign((size_t)n, 0);
             for (int64_t i = 0; i < d->num_blocks; ++i)
-                if (d->block_proj[i] == DL_PROJ_BOX)
+                if (d->block_proj[i] != DL_PROJ_SIMPLEX)
                     for (int64_t e = d->block_off[i]; e < d->block_off[i + 1]; ++e) ebox[e] = 1;
         }
         parallel_for(n, 1 << 20, [&](int64_t lo, int64_t hi) {

@@ -229,15 +229,14 @@ __device__ __forceinline__ void accum(const Lds& s, const GradArgs& g, int j, do
     else accum_tail<CHECK>(g, j, ax, cx, q);
 }
 
-// the projected value of one edge given its block threshold
+// the projected value of one edge given its block threshold: clamp(w (t -
+// tau), 0, u), u = inf on simplex blocks, tau = 0 on box blocks (t - 0 is t,
+// so a box edge is exactly clamp(w t, 0, u))
 template <bool BOX>
 __device__ __forceinline__ double xval(double t, double w, double tau, float u)
 {
-    if (BOX) {
-        const double z = w * t;
-        return z > 0.0 ? (z < (double)u ? z : (double)u) : 0.0;
-    }
     const double z = w * (t - tau);
+    if (BOX) return z > 0.0 ? (z < (double)u ? z : (double)u) : 0.0;
     return z > 0.0 ? z : 0.0;
 }
 
@@ -557,16 +556,112 @@ __device__ __forceinline__ double seg_threshold(const double (&t)[P], const floa
     return tau;
 }
 
+// ---------------------------------------------------------------------------
+// Capped simplex {0 <= x <= u, sum x <= 1} (the reading of the box-cut set):
+// x_e = clamp(w_e (t_e - tau), 0, u_e) with tau = 0 when phi(0) =
+// sum_e clamp(w_e t_e, 0, u_e) <= 1, else the root tau > 0 of phi(tau) = 1.
+// The root is found by variable fixing on a bracket [lo, hi] that holds it
+// (Kiwiel 2008, on the continuous quadratic knapsack): edges with t <= lo sit
+// at 0, edges with t > lo and t - u/w >= hi at their bound u, the others are
+// free.  The free edges' relaxed root tau_F = (sum_F w t + sum_U u - 1) /
+// sum_F w makes the free values sum to what the fixed ones leave; clipping
+// those that leave [0, u] adds dn (from below 0) and removes up (above u), so
+// phi(tau_F) - 1 = dn - up and the root lies above tau_F when dn >= up (lo
+// moves to tau_F: the edges pushed below 0 are fixed there) and below it
+// otherwise (hi moves: the edges above u are fixed at u).  Each step fixes at
+// least one edge; when no free edge leaves [0, u], tau_F is the root and the
+// result satisfies the KKT conditions exactly.  (The oracle uses a different
+// exact method, a breakpoint search.)
+// ---------------------------------------------------------------------------
+// rows that are no edge carry t = -inf: never free, never at a bound
+template <bool HASW>
+__device__ __forceinline__ bool cut_free(double t, float u, float wv, double gamma, double lo, double hi)
+{
+    const double iw = HASW ? gamma / (double)wv : gamma;   // 1/w
+    return t > lo && t - (double)u * iw < hi;
+}
+template <bool HASW>
+__device__ __forceinline__ bool cut_upper(double t, float u, float wv, double gamma, double lo, double hi)
+{
+    const double iw = HASW ? gamma / (double)wv : gamma;
+    return t > lo && !(t - (double)u * iw < hi);
+}
+
+// blocks on S lanes (S = 1: one lane per block); the segments of a wave
+// iterate in lock step, finished ones holding their tau
+template <int S, bool HASW, int P>
+__device__ __forceinline__ double cut_threshold(const double (&t)[P], const float (&u)[P],
+                                               const float (&wv)[HASW ? P : 1], const double gamma,
+                                               const double inv_g)
+{
+    double s0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const double w = HASW ? (double)wv[HASW ? k : 0] * inv_g : inv_g;
+        const double z = w * t[k];
+        s0 += z > 0.0 ? (z < (double)u[k] ? z : (double)u[k]) : 0.0;
+    }
+    s0 = seg_sum<S>(s0);
+    bool live = s0 > 1.0;
+    if (!__builtin_amdgcn_ballot_w64(live)) return 0.0;
+    double lo = 0.0, hi = INFINITY, tau = 0.0;
+#pragma unroll 1
+    for (int rep = 0; rep < P * S + 4; ++rep) {
+        if (!__builtin_amdgcn_ballot_w64(live)) break;
+        double sw = 0.0, swt = 0.0, su = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const float wk = wv[HASW ? k : 0];
+            const double w = HASW ? (double)wk * inv_g : inv_g;
+            const bool fr = cut_free<HASW>(t[k], u[k], wk, gamma, lo, hi);
+            const bool up = cut_upper<HASW>(t[k], u[k], wk, gamma, lo, hi);
+            sw += fr ? w : 0.0;
+            swt += fr ? w * t[k] : 0.0;
+            su += up ? (double)u[k] : 0.0;
+        }
+        sw = seg_sum<S>(sw);
+        swt = seg_sum<S>(swt);
+        su = seg_sum<S>(su);
+        const double tf = sw > 0.0 ? (swt + su - 1.0) / sw : lo;
+        double dn = 0.0, dup = 0.0;
+        int nv = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const float wk = wv[HASW ? k : 0];
+            const double w = HASW ? (double)wk * inv_g : inv_g;
+            const bool fr = cut_free<HASW>(t[k], u[k], wk, gamma, lo, hi);
+            const double z = w * (t[k] - tf);
+            const bool below = fr && z < 0.0, above = fr && z > (double)u[k];
+            dn += below ? -z : 0.0;
+            dup += above ? z - (double)u[k] : 0.0;
+            nv += (below || above) ? 1 : 0;
+        }
+        dn = seg_sum<S>(dn);
+        dup = seg_sum<S>(dup);
+        nv = seg_sum_i<S>(nv);
+        if (live) {
+            tau = tf;
+            if (nv == 0 || !(sw > 0.0)) live = false;
+            else if (dn >= dup) lo = fmax(lo, tf);
+            else hi = fmin(hi, tf);
+        }
+    }
+    return tau;
+}
+
 // projection phase: simplex threshold, then x, the objective and the
 // per-destination sums
-template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, int P>
 __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, const SegGeo& q,
-                                             double gamma, Obj& ob, const LaneVals<VT, CHECK, BOX, HASW, P>& v)
+                                             double gamma, Obj& ob, const LaneVals<VT, CHECK, PJ != 0, HASW, P>& v)
 {
+    constexpr bool BOX = PJ != 0;   // per-edge bounds (box and capped blocks)
     const double inv_g = 1.0 / gamma;
     const double* t = v.t;
     double tau = 0.0;
-    if (S > 1) {
+    if constexpr (PJ == 2) {
+        tau = cut_threshold<S, HASW, P>(v.t, v.u, v.w, gamma, inv_g);
+    } else if (S > 1) {
         if (!BOX) tau = seg_threshold<S, HASW, P>(v.t, v.w, gamma, inv_g);
     } else if (!BOX && !HASW) {
         // uniform weight w = 1/gamma: sum max(0, w t) > 1  <=>  sum max(0, t) > gamma,
@@ -700,10 +795,11 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
 // tiles, each tile's loads all issued before their first use behind a
 // scheduling fence (left to itself the scheduler interleaves each row's loads
 // with its use, one memory round trip per row)
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, int P>
 __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, const Lds& s,
                                            double gamma, Obj& ob)
 {
+    constexpr bool BOX = PJ != 0;
     static_assert(P <= 32, "lane blocks hold at most 32 edges");
     const SegGeo q = seg_geo<1>(it);
     LaneRaw<VT, BOX, HASW, P> r;
@@ -735,7 +831,7 @@ __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, co
             }
         }
     }
-    lane_project<1, VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
+    lane_project<1, VT, CHECK, HASW, TAIL, PJ, P>(g, s, q, gamma, ob, v);
 }
 
 // row class of a group: S = 1 by degree (FP64 storage: at most 8); S > 1 by
@@ -775,10 +871,11 @@ __device__ __forceinline__ Item item_at(const Item& mine, int r)
 // gather lam from memory issue the gathers first, then the prefetch, so that
 // waiting for the gathers (older in the in-order memory counter) never waits
 // for the prefetch as well.  Returns the first entry not processed.
-template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX, int P>
+template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, int P>
 __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int r, const int rn, const Lds& s,
                                         double gamma, Obj& ob)
 {
+    constexpr bool BOX = PJ != 0;
     static_assert(P <= 16, "pipelined lane runs hold at most 16 rows per group");
     constexpr int LG = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : S == 16 ? 4 : S == 32 ? 5 : 6;
     static_assert((1 << LG) == S, "S is a power of two up to 64");
@@ -794,7 +891,7 @@ __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int
         SegGeo qn = q;
         if (r + 1 < rn) {
             const Item nx = item_at(mine, r + 1);
-            if ((nx.proj == 1) == BOX && nx.kind == ITEM_LANE && nx.lg == LG &&
+            if (nx.proj == PJ && nx.kind == ITEM_LANE && nx.lg == LG &&
                 lane_class<VT, HASW, TAIL>(nx.d, LG) == P) {
                 more = true;
                 qn = seg_geo<S>(nx);
@@ -816,7 +913,7 @@ __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int
             lane_t_gathered<S>(q, cur, lam, v);
         }
         __builtin_amdgcn_sched_barrier(0);
-        lane_project<S, VT, CHECK, HASW, TAIL, BOX, P>(g, s, q, gamma, ob, v);
+        lane_project<S, VT, CHECK, HASW, TAIL, PJ, P>(g, s, q, gamma, ob, v);
         if (!more) break;
         cur = nxt;
         q = qn;
@@ -842,13 +939,145 @@ __device__ __forceinline__ double edge_t(const GradArgs& g, const Lds& s, int64_
     return -(c + a * get_lam<CHECK, TAIL>(s, g, j));
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+// three sums over the whole workgroup (all threads call it)
+__device__ __forceinline__ void wg_sum3d(double& a, double& b, double& c, double* red)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = a;
+        red[kWaves + w] = b;
+        red[2 * kWaves + w] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int i = 0; i < kWaves; ++i) {
+        a += red[i];
+        b += red[kWaves + i];
+        c += red[2 * kWaves + i];
+    }
+}
+
+// capped-simplex threshold of a WG block held in registers (edge e = k kWG +
+// tid); every thread gets the same sums, so the loop is uniform
+template <int RW, bool HASW>
+__device__ __forceinline__ double wg_cut_threshold(const double (&t)[RW], const float (&u)[RW],
+                                                  const float (&wv)[HASW ? RW : 1], const double gamma,
+                                                  const double inv_g, double* red)
+{
+    double s0 = 0.0, z0 = 0.0, z1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const double w = HASW ? (double)wv[HASW ? k : 0] * inv_g : inv_g;
+        const double z = w * t[k];
+        s0 += z > 0.0 ? (z < (double)u[k] ? z : (double)u[k]) : 0.0;
+    }
+    wg_sum3d(s0, z0, z1, red);
+    if (!(s0 > 1.0)) return 0.0;
+    double lo = 0.0, hi = INFINITY, tau = 0.0;
+#pragma unroll 1
+    for (int rep = 0; rep < RW * kWG + 4; ++rep) {
+        double sw = 0.0, swt = 0.0, su = 0.0;
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const float wk = wv[HASW ? k : 0];
+            const double w = HASW ? (double)wk * inv_g : inv_g;
+            const bool fr = cut_free<HASW>(t[k], u[k], wk, gamma, lo, hi);
+            const bool up = cut_upper<HASW>(t[k], u[k], wk, gamma, lo, hi);
+            sw += fr ? w : 0.0;
+            swt += fr ? w * t[k] : 0.0;
+            su += up ? (double)u[k] : 0.0;
+        }
+        wg_sum3d(sw, swt, su, red);
+        const double tf = sw > 0.0 ? (swt + su - 1.0) / sw : lo;
+        double dn = 0.0, dup = 0.0, nv = 0.0;
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const float wk = wv[HASW ? k : 0];
+            const double w = HASW ? (double)wk * inv_g : inv_g;
+            const bool fr = cut_free<HASW>(t[k], u[k], wk, gamma, lo, hi);
+            const double z = w * (t[k] - tf);
+            const bool below = fr && z < 0.0, above = fr && z > (double)u[k];
+            dn += below ? -z : 0.0;
+            dup += above ? z - (double)u[k] : 0.0;
+            nv += (below || above) ? 1.0 : 0.0;
+        }
+        wg_sum3d(dn, dup, nv, red);
+        tau = tf;
+        if (nv == 0.0 || !(sw > 0.0)) break;
+        if (dn >= dup) lo = fmax(lo, tf);
+        else hi = fmin(hi, tf);
+    }
+    return tau;
+}
+
+// the same for WG blocks beyond the register form: t recomputed from memory
+// on every pass (the block stays in L2 between passes)
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+__device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const Lds& s, const int64_t base,
+                                                      const int d, const double gamma, const double inv_g)
+{
+    double s0 = 0.0, z0 = 0.0, z1 = 0.0;
+    for (int e = threadIdx.x; e < d; e += kWG) {
+        double w;
+        const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+        const double uu = (double)g.U[base + e];
+        const double z = w * t;
+        s0 += z > 0.0 ? (z < uu ? z : uu) : 0.0;
+    }
+    wg_sum3d(s0, z0, z1, s.red);
+    if (!(s0 > 1.0)) return 0.0;
+    double lo = 0.0, hi = INFINITY, tau = 0.0;
+#pragma unroll 1
+    for (int rep = 0; rep < d + 4; ++rep) {
+        double sw = 0.0, swt = 0.0, su = 0.0;
+        for (int e = threadIdx.x; e < d; e += kWG) {
+            double w;
+            const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+            const float uk = g.U[base + e];
+            const float wk = HASW ? g.IV[base + e] : 1.0f;
+            const bool fr = cut_free<HASW>(t, uk, wk, gamma, lo, hi);
+            const bool up = cut_upper<HASW>(t, uk, wk, gamma, lo, hi);
+            sw += fr ? w : 0.0;
+            swt += fr ? w * t : 0.0;
+            su += up ? (double)uk : 0.0;
+        }
+        wg_sum3d(sw, swt, su, s.red);
+        const double tf = sw > 0.0 ? (swt + su - 1.0) / sw : lo;
+        double dn = 0.0, dup = 0.0, nv = 0.0;
+        for (int e = threadIdx.x; e < d; e += kWG) {
+            double w;
+            const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+            const float uk = g.U[base + e];
+            const float wk = HASW ? g.IV[base + e] : 1.0f;
+            const bool fr = cut_free<HASW>(t, uk, wk, gamma, lo, hi);
+            const double z = w * (t - tf);
+            const bool below = fr && z < 0.0, above = fr && z > (double)uk;
+            dn += below ? -z : 0.0;
+            dup += above ? z - (double)uk : 0.0;
+            nv += (below || above) ? 1.0 : 0.0;
+        }
+        wg_sum3d(dn, dup, nv, s.red);
+        tau = tf;
+        if (nv == 0.0 || !(sw > 0.0)) break;
+        if (dn >= dup) lo = fmax(lo, tf);
+        else hi = fmin(hi, tf);
+    }
+    return tau;
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, const Lds& s, double gamma, Obj& ob)
 {
+    constexpr bool BOX = PJ != 0;
     const int d = uni(it.d);
     const int64_t base = uni64(it.base);
     const double inv_g = 1.0 / gamma;
     double tau = 0.0;
+    if constexpr (PJ == 2) tau = wg_cut_threshold_mem<VT, CHECK, HASW, TAIL>(g, s, base, d, gamma, inv_g);
     if (!BOX) {
         double s0 = 0.0, mx = -INFINITY;
         for (int e = threadIdx.x; e < d; e += kWG) {
@@ -960,13 +1189,15 @@ __device__ __forceinline__ void wg_t(const int d, const LaneRaw<VT, BOX, HASW, R
     }
 }
 
-template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ void wg_project(const GradArgs& g, const Lds& s, const int64_t base, const int d,
-                                           const double gamma, Obj& ob, const LaneVals<VT, CHECK, BOX, HASW, RW>& v)
+                                           const double gamma, Obj& ob, const LaneVals<VT, CHECK, PJ != 0, HASW, RW>& v)
 {
+    constexpr bool BOX = PJ != 0;
     const double inv_g = 1.0 / gamma;
     const double* t = v.t;
     double tau = 0.0;
+    if constexpr (PJ == 2) tau = wg_cut_threshold<RW, HASW>(v.t, v.u, v.w, gamma, inv_g, s.red);
     if (!BOX) {
         // uniform weights: the two largest t; with the second at most tau_0 =
         // max t - 1/w only the largest is active and tau_0 is the threshold
@@ -1045,9 +1276,10 @@ __device__ __forceinline__ int wg_class(int d) { return d <= 2 * kWG ? 2 : d <= 
 
 // WG items i, i+1, ... of class RW and one projection type; returns the first
 // item not processed
-template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, const Lds& s, double gamma, Obj& ob)
 {
+    constexpr bool BOX = PJ != 0;
     constexpr bool EARLY = !TAIL;   // lam from LDS
     Item it = g.items[i];
     int64_t base = uni64(it.base);
@@ -1062,7 +1294,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
         if (i + 1 < i1) {
             const Item nx = g.items[i + 1];
             const int nd = uni(nx.d);
-            if ((nx.proj == 1) == BOX && nd <= 8 * kWG && wg_class(nd) == RW) {
+            if (nx.proj == PJ && nd <= 8 * kWG && wg_class(nd) == RW) {
                 more = true;
                 bn = uni64(nx.base);
                 dn = nd;
@@ -1085,7 +1317,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
         }
         __builtin_amdgcn_sched_barrier(0);
         wg_t<RW>(d, cur, lam, v);
-        wg_project<RW, VT, CHECK, HASW, TAIL, BOX>(g, s, base, d, gamma, ob, v);
+        wg_project<RW, VT, CHECK, HASW, TAIL, PJ>(g, s, base, d, gamma, ob, v);
         if (!more) break;
         cur = nxt;
         base = bn;
@@ -1100,7 +1332,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
 // the fused gradient kernel: one workgroup per chunk
 // ---------------------------------------------------------------------------
 // lane items from batch entry r on; returns the first entry not processed
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool BOX>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine, const int r, const int rn,
                                              const Item& it, const Lds& s, double gamma, Obj& ob)
 {
@@ -1113,33 +1345,33 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
     constexpr int CAP = lane_cap(W8, HASW, TAIL);
     const int cls = lane_class<VT, HASW, TAIL>(it.d, it.lg);
     if (it.lg == 2) {
-        if (cls == 8) return lane_run<4, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
-        return lane_run<4, VT, CHECK, HASW, TAIL, BOX, RMAX>(g, mine, r, rn, s, gamma, ob);
+        if (cls == 8) return lane_run<4, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
+        return lane_run<4, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
     }
     if (it.lg == 4) {
-        if (cls == 8) return lane_run<16, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
-        return lane_run<16, VT, CHECK, HASW, TAIL, BOX, RMAX>(g, mine, r, rn, s, gamma, ob);
+        if (cls == 8) return lane_run<16, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
+        return lane_run<16, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
     }
     if (it.lg == 6) {
-        if (cls == 8) return lane_run<64, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
-        return lane_run<64, VT, CHECK, HASW, TAIL, BOX, RMAX>(g, mine, r, rn, s, gamma, ob);
+        if (cls == 8) return lane_run<64, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
+        return lane_run<64, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
     }
     switch (cls) {
-    case 4: return lane_run<1, VT, CHECK, HASW, TAIL, BOX, 4>(g, mine, r, rn, s, gamma, ob);
-    case 8: return lane_run<1, VT, CHECK, HASW, TAIL, BOX, 8>(g, mine, r, rn, s, gamma, ob);
+    case 4: return lane_run<1, VT, CHECK, HASW, TAIL, PJ, 4>(g, mine, r, rn, s, gamma, ob);
+    case 8: return lane_run<1, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
     case 12:
-        if constexpr (RMAX >= 12) return lane_run<1, VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
-        lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 12>(g, it, s, gamma, ob);
+        if constexpr (RMAX >= 12) return lane_run<1, VT, CHECK, HASW, TAIL, PJ, W8 ? 8 : 12>(g, mine, r, rn, s, gamma, ob);
+        lane_group<VT, CHECK, HASW, TAIL, PJ, W8 ? 8 : 12>(g, it, s, gamma, ob);
         return r + 1;
     case 16:
-        if constexpr (RMAX >= 16) return lane_run<1, VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
-        lane_group<VT, CHECK, HASW, TAIL, BOX, W8 ? 8 : 16>(g, it, s, gamma, ob);
+        if constexpr (RMAX >= 16) return lane_run<1, VT, CHECK, HASW, TAIL, PJ, W8 ? 8 : 16>(g, mine, r, rn, s, gamma, ob);
+        lane_group<VT, CHECK, HASW, TAIL, PJ, W8 ? 8 : 16>(g, it, s, gamma, ob);
         return r + 1;
     case 24:
-        if constexpr (CAP > 16) lane_group<VT, CHECK, HASW, TAIL, BOX, 24>(g, it, s, gamma, ob);
+        if constexpr (CAP > 16) lane_group<VT, CHECK, HASW, TAIL, PJ, 24>(g, it, s, gamma, ob);
         return r + 1;
     default:
-        if constexpr (CAP > 24) lane_group<VT, CHECK, HASW, TAIL, BOX, 32>(g, it, s, gamma, ob);
+        if constexpr (CAP > 24) lane_group<VT, CHECK, HASW, TAIL, PJ, 32>(g, it, s, gamma, ob);
         return r + 1;
     }
 }
@@ -1211,8 +1443,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
             for (int r = 0; r < rn;) {
                 const Item it = item_at(mine, r);
-                if (it.proj == 1) r = lane_dispatch<VT, CHECK, HASW, TAIL, true>(g, mine, r, rn, it, s, gamma, ob);
-                else r = lane_dispatch<VT, CHECK, HASW, TAIL, false>(g, mine, r, rn, it, s, gamma, ob);
+                if (it.proj == 1) r = lane_dispatch<VT, CHECK, HASW, TAIL, 1>(g, mine, r, rn, it, s, gamma, ob);
+                else if (it.proj == 2) r = lane_dispatch<VT, CHECK, HASW, TAIL, 2>(g, mine, r, rn, it, s, gamma, ob);
+                else r = lane_dispatch<VT, CHECK, HASW, TAIL, 0>(g, mine, r, rn, it, s, gamma, ob);
             }
         }
     }
@@ -1220,20 +1453,25 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
         const Item it = g.items[i];
         const int d = uni(it.d);
         if (d > 8 * kWG) {
-            if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, true>(g, it, s, gamma, ob);
-            else wg_block<VT, CHECK, HASW, TAIL, false>(g, it, s, gamma, ob);
+            if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, 1>(g, it, s, gamma, ob);
+            else if (it.proj == 2) wg_block<VT, CHECK, HASW, TAIL, 2>(g, it, s, gamma, ob);
+            else wg_block<VT, CHECK, HASW, TAIL, 0>(g, it, s, gamma, ob);
             ++i;
             continue;
         }
         const int rw = wg_class(d);
         if (it.proj == 1) {
-            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, true>(g, i, ch.b1, s, gamma, ob);
-            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, true>(g, i, ch.b1, s, gamma, ob);
-            else i = wg_run<8, VT, CHECK, HASW, TAIL, true>(g, i, ch.b1, s, gamma, ob);
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
+        } else if (it.proj == 2) {
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
         } else {
-            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, false>(g, i, ch.b1, s, gamma, ob);
-            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, false>(g, i, ch.b1, s, gamma, ob);
-            else i = wg_run<8, VT, CHECK, HASW, TAIL, false>(g, i, ch.b1, s, gamma, ob);
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
         }
     }
     __syncthreads();

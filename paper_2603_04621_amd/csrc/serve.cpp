@@ -121,7 +121,7 @@ static size_t estimate_bytes(const dl_problem_desc* d, const dl_problem_opts* o)
     const size_t es = o->storage == DL_F64 ? 8 : (o->storage == DL_F32 ? 4 : 2);
     const size_t n = (size_t)d->n, m = (size_t)d->m, nb = (size_t)d->num_blocks;
     bool has_box = false;
-    for (size_t i = 0; i < nb && !has_box; ++i) has_box = d->block_proj[i] == DL_PROJ_BOX;
+    for (size_t i = 0; i < nb && !has_box; ++i) has_box = d->block_proj[i] != DL_PROJ_SIMPLEX;
     size_t bytes = n * (2 * es + 4 + 8) + (has_box ? 4 * n : 0) + (o->primal_scale ? 4 * n : 0);
     bytes += nb * sizeof(Item);
     const size_t nch = std::min<size_t>(2 * 256, std::max<size_t>(1, (n + 32767) / 32768));

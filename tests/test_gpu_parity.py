@@ -105,7 +105,8 @@ def assert_x_close(inst, lam, gamma, v, xo, xg):
 
 def check_active_sets(inst, xo, xg, thr=1e-5, band=2e-5):
     u = inst.upper if inst.upper is not None else np.ones(inst.n)
-    box = np.repeat(inst.block_proj == I.PROJ_BOX, np.diff(inst.block_off))
+    # edges with a bound u (box and capped blocks) have a third class at u
+    box = np.repeat(inst.block_proj != I.PROJ_SIMPLEX, np.diff(inst.block_off))
     cls_o = np.where(xo <= thr, 0, np.where(box & (u - xo <= thr), 2, 1))
     cls_g = np.where(xg <= thr, 0, np.where(box & (u - xg <= thr), 2, 1))
     far = (np.abs(xo - thr) > band) & (~box | (np.abs((u - xo) - thr) > band))
@@ -114,7 +115,7 @@ def check_active_sets(inst, xo, xg, thr=1e-5, band=2e-5):
     sums_o = np.add.reduceat(xo, inst.block_off[:-1]) if inst.n else np.zeros(0)
     sums_g = np.add.reduceat(xg, inst.block_off[:-1]) if inst.n else np.zeros(0)
     nonempty = np.diff(inst.block_off) > 0
-    simp = (inst.block_proj == I.PROJ_SIMPLEX) & nonempty
+    simp = (inst.block_proj != I.PROJ_BOX) & nonempty      # blocks with sum x <= 1
     bind_o = sums_o >= 1 - thr
     bind_g = sums_g >= 1 - thr
     farb = np.abs(sums_o - (1 - thr)) > band
@@ -262,6 +263,46 @@ def test_edge_cases(O, dev):
     for lam in (np.zeros(big.m), lam_for(big, 2, 0.7)):
         compare(O, big, "f32", lam, 1e-2)
         compare(O, big, "f64", lam, 1e-2, grad_tol=1e-5)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_grad_capped_all_paths(O, dev, storage):
+    """Capped-simplex blocks {0 <= x <= u, sum x <= 1} beside simplex and box
+    blocks on every work path: one-lane blocks, blocks on 4, 16 and 64 lanes,
+    workgroup blocks in registers and beyond them (multi-pass), at gammas
+    where the caps bind, the sum binds, or neither."""
+    rng = np.random.default_rng(31)
+    deg = np.concatenate([rng.integers(1, 33, size=2000), rng.integers(33, 65, size=120),
+                          rng.integers(65, 257, size=50), rng.integers(257, 1025, size=16),
+                          rng.integers(1025, 4096, size=6), np.array([4500, 5200, 6000])])
+    rng.shuffle(deg)
+    inst = I._finish("capped", 31, deg.size, 7000, deg, rng, I.zipf_cdf(7000, 1.1),
+                     I._neg_lognormal, I._lognormal_a, 0.3, box_frac=0.2, capped_frac=0.5,
+                     capacity="greedy", seed_key=[31, 1])
+    capped = inst.block_proj == I.PROJ_CAPPED
+    assert capped.sum() > 100 and np.max(np.diff(inst.block_off)[capped]) > 4096
+    with gpu_problem(inst, storage) as p:
+        info = p.info()
+    assert info["lane_groups"] > 0 and info["seg_groups"] > 0 and info["wg_blocks"] > 0
+    for seed, gamma in ((1, 1e-1), (2, 1e-2), (3, 1e-3)):
+        compare(O, inst, storage, lam_for(inst, seed, 1.0), gamma,
+                g_tol=1e-12 if storage == "f64" else 1e-6)
+    # huge prices: every x = 0; zero prices: every block's positive part
+    compare(O, inst, storage, np.zeros(inst.m), 1e-2)
+    compare(O, inst, storage, np.full(inst.m, 1e6), 1e-2)
+
+
+def test_grad_capped_rows_beyond_lds_and_primal_scale(O, dev):
+    """Capped blocks with destinations beyond LDS (tail variant) and with
+    per-edge weights w = 1/(gamma v^2) (primal scaling)."""
+    inst = I.heavy(I=12_000, J=20_000, dmax=4096, capacity="greedy", capped_frac=0.4)
+    with gpu_problem(inst) as p:
+        assert p.info()["lds_rows"] < inst.m
+    compare(O, inst, "f32", lam_for(inst, 41, 2.0), 1e-2)
+    small = I.random_small(42, I=800, J=50, dmax=300, box_frac=0.2, capped_frac=0.5)
+    v = np.random.default_rng(4).uniform(0.5, 2.0, size=small.n)
+    compare(O, small, "f64", lam_for(small, 43), 1e-2, primal_scale=2, v=v)
+    compare(O, small, "f64", lam_for(small, 44), 1e-2, primal_scale=1)
 
 
 def tie_instance(gamma, seed=11):
@@ -416,6 +457,41 @@ def test_solve_fp32_converges_and_matches_evaluation(O, dev):
     ev = O.dual_eval(inst.rounded("f32"), lam.cpu().numpy(), r.gamma)
     assert abs(ev.g - r.g) <= 1e-6 * max(1.0, abs(ev.g))
     assert ev.rel_gap <= 1.01e-4
+
+
+def test_solve_capped_blocks_gap_certified(O, dev):
+    """A continuation solve over simplex, box and capped-simplex blocks (FP32
+    storage): at the GPU's final lam the oracle, on the stored data,
+    reproduces g and the reported gap (the capped set is down-closed, so the
+    restored point is feasible and the gap is a certificate)."""
+    from paper_2603_04621_amd.api import SolveSettings
+    inst = I.heavy(I=40_000, J=2_000, dmax=512, capacity="greedy", capped_frac=0.4)
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-3, n_stages=5, stage_iters=2000,
+                      stage_tol=1e-3, tol_rel_gap=1e-4, max_iters=3000, check_every=10,
+                      preset="natural")
+    with gpu_problem(inst, "f32") as p:
+        lam, r = p.solve(s)
+    assert r.rel_gap < 1e-3, r
+    ev = O.dual_eval(inst.rounded("f32"), lam.cpu().numpy(), r.gamma)
+    assert abs(ev.g - r.g) <= 1e-6 * max(1.0, abs(ev.g))
+    assert abs(ev.rel_gap - r.rel_gap) <= 1e-6
+
+
+def test_solve_capped_trajectory_fp64(O, dev):
+    """300 accelerated iterations over capped-simplex, box and simplex blocks
+    with FP64 storage follow the oracle's g (every iteration), gap and lam."""
+    from paper_2603_04621_amd.api import SolveSettings
+    inst = I.random_small(45, I=3_000, J=80, dmax=40, box_frac=0.2, capped_frac=0.5)
+    s = SolveSettings(gamma0=1e-2, gamma_final=1e-2, max_iters=300, check_every=10,
+                      tol_rel_gap=-1.0, max_step=1e-2, init_step=1e-4, trace=True)
+    r_or = O.solve(inst, oracle_opts(O, s))
+    with gpu_problem(inst, "f64") as p:
+        lam, r = p.solve(s)
+    assert r.iters == 300 == r_or.iters
+    rel = np.abs(r.trace[:, 0] - r_or.trace[:, 0]) / np.maximum(1.0, np.abs(r_or.trace[:, 0]))
+    assert rel.max() <= 1e-6, (rel.max(), int(rel.argmax()))
+    assert abs(r.rel_gap - r_or.rel_gap) <= 1e-6
+    assert lam_close(lam.cpu().numpy(), r_or.lam)
 
 
 def test_solve_warm_start_and_max_iters(O, dev):
