@@ -32,6 +32,10 @@ Workload recipes (all draws in float64 from numpy's PCG64, seed
              min(J, 1+Poisson(9)), as ``large`` otherwise.
 * ``serve``  request stream, Poisson arrivals, I log-uniform, J=I//500,
              70/30 simplex/box blocks, as ``heavy`` otherwise.
+* ``appendix_b`` the paper's own synthetic construction (Appendix B):
+             lognormal resource breadths, Poisson resource degrees, values
+             min(v_j u_i eps_ij, c_max), a_ij = s_j c_ij with lognormal s_j,
+             greedy-load capacities; constants in APPB_* below.
 
 Every generator takes explicit sizes so the same recipe can be drawn at a
 scale the oracle finishes in seconds.
@@ -225,6 +229,23 @@ def distinct_destinations(seed_key, deg: np.ndarray, J: int, cdf: np.ndarray) ->
     return out
 
 
+def counting_order(key: np.ndarray, nkeys: int) -> np.ndarray:
+    """Stable order of the positions of `key` (int64 in [0, nkeys)) by key:
+    what np.argsort(key, kind="stable") returns, in O(n)."""
+    import ctypes
+    lib = _sampler_lib()
+    f = lib.dl_counting_order
+    f.restype = ctypes.c_int64
+    f.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                  ctypes.c_void_p]
+    key = np.ascontiguousarray(key, dtype=np.int64)
+    out = np.empty(key.shape[0], dtype=np.int64)
+    cnt = np.empty(int(nkeys) + 1, dtype=np.int64)
+    if f(key.shape[0], key.ctypes.data, int(nkeys), cnt.ctypes.data, out.ctypes.data) != 0:
+        raise ValueError("key out of range")
+    return out
+
+
 def greedy_capacity(dst, a, block_off, J, seed_key, eps: float = 1e-2) -> np.ndarray:
     """Capacities of the paper's synthetic construction (Appendix B): every
     source sends its largest a_e to that edge's destination, giving the greedy
@@ -400,10 +421,72 @@ def random_small(seed: int, I: int, J: int, dmax: int, box_frac: float = 0.5,
                    capped_frac=capped_frac)
 
 
+# Constants of the Appendix B construction that the paper leaves unstated
+# (chosen here; all lognormals have location 0): spread of the resource
+# breadths, of the resource value scales v_j, of the request factors u_i, of
+# the edge noise eps_ij and of the per-resource coefficient scales s_j, the
+# value cap c_max, and the small constant added to the greedy load.
+APPB_SIGMA_BREADTH = 1.0
+APPB_SIGMA_V = 0.5
+APPB_SIGMA_U = 0.5
+APPB_SIGMA_EPS = 0.25
+APPB_SIGMA_S = 1.5
+APPB_CMAX = 10.0
+APPB_EPS = 1e-2
+
+
+def appendix_b(I: int = 1_000_000, J: int = 2_000, nu: float = 10.0,
+               seed: int = SEED_BASE + 6) -> Instance:
+    """The synthetic construction of Appendix B ("Synthetic LP construction",
+    "Source capacities and right-hand side"):
+
+    * resource j gets a lognormal breadth; normalised, they give p_j;
+    * K_j ~ Poisson(p_j I nu), truncated at I, distinct requests drawn
+      uniformly for resource j (nu = nonzeros per request on average);
+    * on edge (i, j): value min(v_j u_i eps_ij, c_max) with lognormal v_j,
+      u_i, eps_ij; the LP cost is its negative (a maximisation of value);
+    * a_ij = s_j * value with a lognormal per-resource s_j, so rows differ in
+      support and in magnitude by orders;
+    * b_j = rho_j (l_j + eps), rho_j ~ U[0.5, 1], from the greedy load l_j
+      (each request's largest a_ij sent to its resource);
+    * one simplex block per request (requests without edges have empty blocks).
+    """
+    rng = np.random.default_rng(seed)
+    breadth = rng.lognormal(0.0, APPB_SIGMA_BREADTH, size=J)
+    p = breadth / breadth.sum()
+    K = np.minimum(rng.poisson(p * I * nu), I).astype(np.int64)
+    # distinct requests per resource (resource-major), then source-major order
+    req = np.empty(int(K.sum()), dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(K)])
+    for j in range(J):
+        if K[j]:
+            req[off[j]:off[j + 1]] = rng.choice(I, size=int(K[j]), replace=False)
+    res = np.repeat(np.arange(J, dtype=np.int64), K)
+    order = counting_order(req, I)       # by request, resources ascending within
+    req, res = req[order], res[order]
+    n = int(req.shape[0])
+    v = rng.lognormal(0.0, APPB_SIGMA_V, size=J)
+    u = rng.lognormal(0.0, APPB_SIGMA_U, size=I)
+    eps = rng.lognormal(0.0, APPB_SIGMA_EPS, size=n)
+    val = np.minimum(v[res] * u[req] * eps, APPB_CMAX)
+    sj = rng.lognormal(0.0, APPB_SIGMA_S, size=J)
+    a = sj[res] * val
+    c = -val
+    deg = np.bincount(req, minlength=I).astype(np.int64)
+    block_off = np.zeros(I + 1, dtype=np.int64)
+    np.cumsum(deg, out=block_off[1:])
+    dst = res.astype(np.int32)
+    b = greedy_capacity(dst, a, block_off, J, [seed, 2], eps=APPB_EPS)
+    return Instance(J, n, dst, a, c, b, block_off, np.zeros(I, dtype=np.uint8), None,
+                    "appendix_b", seed, {"I": I, "J": J, "nu": nu, "capacity": "greedy",
+                                         "K": K, "s": sj})
+
+
 CONFIGS: dict[str, Callable[..., Instance]] = {
     "tiny": tiny,
     "large": large,
     "heavy": heavy,
+    "appendix_b": appendix_b,
 }
 
 

@@ -67,3 +67,18 @@ int64_t dl_gen_distinct(int64_t I, const int64_t* deg, int64_t J, const double* 
     if (n_fallback) *n_fallback = fb;
     return k;
 }
+
+/* Stable counting order: out[k] lists the positions q (0..n-1) with key[q] = 0
+ * first, then key 1, ..., each group in increasing q.  count[nkeys + 1] is
+ * scratch.  Returns 0, or -2 on a key outside [0, nkeys). */
+int64_t dl_counting_order(int64_t n, const int64_t* key, int64_t nkeys, int64_t* count, int64_t* out)
+{
+    for (int64_t k = 0; k <= nkeys; ++k) count[k] = 0;
+    for (int64_t q = 0; q < n; ++q) {
+        if (key[q] < 0 || key[q] >= nkeys) return -2;
+        ++count[key[q] + 1];
+    }
+    for (int64_t k = 0; k < nkeys; ++k) count[k + 1] += count[k];
+    for (int64_t q = 0; q < n; ++q) out[count[key[q]]++] = q;
+    return 0;
+}

@@ -305,6 +305,33 @@ def test_grad_capped_rows_beyond_lds_and_primal_scale(O, dev):
     compare(O, small, "f64", lam_for(small, 44), 1e-2, primal_scale=1)
 
 
+def test_grad_appendix_b_workload(O, dev):
+    """The paper's own synthetic construction (Appendix B): row norms that
+    differ by orders of magnitude, Poisson resource degrees; prices scaled
+    per row (lam_j ~ Exp(1) / s_j) so that every row has active edges."""
+    inst = I.appendix_b(I=60_000, J=400, seed=4621)
+    rng = np.random.default_rng(52)
+    lam = rng.exponential(1.0, size=inst.m) / inst.meta["s"]
+    for storage, gamma in (("f64", 1e-2), ("f32", 1e-2), ("f32", 1e-3), ("bf16", 1e-2)):
+        compare(O, inst, storage, lam, gamma, g_tol=1e-12 if storage == "f64" else 1e-6)
+
+
+def test_solve_appendix_b_gap_certified(O, dev):
+    """Continuation to gap 1e-4 on the Appendix B workload (Jacobi rows):
+    the oracle at the GPU's final prices reproduces g and certifies the gap."""
+    from paper_2603_04621_amd.api import SolveSettings
+    inst = I.appendix_b(I=60_000, J=400, seed=4622)
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-2, n_stages=4, stage_iters=2000,
+                      stage_tol=1e-3, tol_rel_gap=1e-4, max_iters=8000, check_every=10,
+                      preset="natural")
+    with gpu_problem(inst, "f32") as p:
+        lam, r = p.solve(s)
+    assert r.converged, r
+    ev = O.dual_eval(inst.rounded("f32"), lam.cpu().numpy(), r.gamma)
+    assert abs(ev.g - r.g) <= 1e-6 * max(1.0, abs(ev.g))
+    assert ev.rel_gap <= 1.01e-4
+
+
 def tie_instance(gamma, seed=11):
     """Blocks of every item kind (lam = 0, a = 1, so t = -c) with the largest
     t = 3/4 and the second 3/4 (a tie), 3/4 - gamma/2 or 3/4 - 3 gamma/2; the
