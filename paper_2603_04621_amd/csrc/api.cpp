@@ -279,7 +279,9 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
         const int64_t deg = d->block_off[i + 1] - d->block_off[i];
         const int pr = d->block_proj[i];
         if (deg == 0) continue;
-        const int lg = block_lg(deg, cap, rmax);
+        // capped-simplex blocks: smaller one-lane and per-lane classes
+        const int lg = pr == DL_PROJ_CAPPED ? block_lg(deg, std::min(cap, kCutLaneCap), std::min(rmax, kCutRmax))
+                                            : block_lg(deg, cap, rmax);
         if (lg >= 0) bucket(lg, pr, deg).push_back(i);
         else wgb.push_back({(int64_t)pr, i});
     }
@@ -499,6 +501,7 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     }
     // per-edge bounds are stored when any block has them (box and capped)
     for (int64_t i = 0; i < d->num_blocks && !p->has_box; ++i) p->has_box = d->block_proj[i] != DL_PROJ_SIMPLEX;
+    for (int64_t i = 0; i < d->num_blocks && !p->has_cut; ++i) p->has_cut = d->block_proj[i] == DL_PROJ_CAPPED;
 
     // work items and chunks
     const int cus = device_cus(p->device);
@@ -896,7 +899,7 @@ hipError_t enqueue_iteration(dl_problem* p, const SolveParams& prm, int check, d
     GradArgs g = grad_args(p, p->lam_eval, gptr, 0.0, done, nullptr);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-    if ((e = launch_grad(g, p->storage, check != 0, p->has_w != 0, s)) != hipSuccess) return e;
+    if ((e = launch_grad(g, p->storage, check != 0, p->has_w != 0, p->has_cut != 0, s)) != hipSuccess) return e;
     if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
     ReduceArgs r = reduce_args(p, check, 0, p->lam_eval, gptr, 0.0, done, nullptr);
     AgdArgs a = agd_args(p, prm, check, trace);
@@ -960,7 +963,7 @@ extern "C" dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, doubl
     const int check = eval_host ? 1 : 0;
     HIP_TRY(dl::launch_permute_in(lambda_dev, p->orig, p->J, p->lam_int, s), "permute lambda");
     GradArgs g = dlh::grad_args(p, p->lam_int, nullptr, gamma, nullptr, x_dev);
-    HIP_TRY(launch_grad(g, p->storage, check != 0, p->has_w != 0, s), "gradient kernel");
+    HIP_TRY(launch_grad(g, p->storage, check != 0, p->has_w != 0, p->has_cut != 0, s), "gradient kernel");
     ReduceArgs r = dlh::reduce_args(p, check, 1, p->lam_int, nullptr, gamma, nullptr, grad_dev);
     HIP_TRY(launch_reduce(r, p->nblk2, s), "reduce kernel");
     if (eval_host) {
@@ -994,7 +997,7 @@ extern "C" dl_status dl_time_grad_kernel(dl_problem* p, const double* lambda_dev
     for (int i = 0; i < iters && st == DL_OK; ++i) {
         GradArgs g = dlh::grad_args(p, p->lam_int, nullptr, gamma, nullptr, nullptr);
         hipError_t e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = launch_grad(g, p->storage, check != 0, p->has_w != 0, s);
+        if (e == hipSuccess) e = launch_grad(g, p->storage, check != 0, p->has_w != 0, p->has_cut != 0, s);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         ReduceArgs r = dlh::reduce_args(p, check, 1, p->lam_int, nullptr, gamma, nullptr, p->lam);
         if (e == hipSuccess) e = launch_reduce(r, p->nblk2, s);

@@ -84,9 +84,9 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
     }
     // groups by kernel variant (storage, weights, rows beyond LDS: the layout
     // of each problem matches its variant); the largest problems go first
-    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < n; ++k)
-        by[{probs[k]->storage, probs[k]->has_w, probs[k]->K < probs[k]->J ? 1 : 0}].push_back(k);
+        by[{probs[k]->storage, probs[k]->has_w, probs[k]->K < probs[k]->J ? 1 : 0, probs[k]->has_cut}].push_back(k);
     std::vector<int2> ct, rb;
     for (auto& kv : by) {
         auto idx = kv.second;
@@ -95,6 +95,7 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
         G.storage = std::get<0>(kv.first);
         G.has_w = std::get<1>(kv.first);
         G.tail = std::get<2>(kv.first);
+        G.cut = std::get<3>(kv.first);
         G.lds = 0;
         G.c0 = (int)ct.size();
         // round-robin over problems so long chunks of big problems start early
@@ -156,7 +157,7 @@ hipError_t BatchRunner::enqueue_iteration(int check, hipStream_t s) const
     hipError_t e;
     for (const Group& G : groups_)
         if ((e = launch_grad_batch(gtab_, ctab_ + G.c0, G.nblocks, G.lds, G.storage, check != 0, G.has_w != 0,
-                                   G.tail != 0, s)) != hipSuccess)
+                                   G.tail != 0, G.cut != 0, s)) != hipSuccess)
             return e;
     if ((e = launch_reduce_batch(rtab_[check ? 1 : 0], rbt_, nrb_, s)) != hipSuccess) return e;
     return launch_agd_batch(atab_[check ? 1 : 0], (int)probs_.size(), s);

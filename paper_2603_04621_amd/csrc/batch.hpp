@@ -1,5 +1,5 @@
 // Batched iteration over several problems: one fused gradient launch per
-// (storage, primal-scale) group, one reduction launch and one ascent launch
+// kernel-variant group (storage, primal scale, rows beyond LDS, capped blocks), one reduction launch and one ascent launch
 // per iteration, all driven by per-problem argument tables on the device.
 // Each problem keeps its own chunking, reduction order and FP64 state, so a
 // problem's iterates are the same alone and in a batch.
@@ -29,7 +29,7 @@ public:
 
 private:
     struct Group {
-        int storage, has_w, tail;
+        int storage, has_w, tail, cut;
         int c0, nblocks;
         size_t lds;
     };

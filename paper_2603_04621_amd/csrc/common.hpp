@@ -53,6 +53,12 @@ constexpr int seg_rmax(bool f64, bool has_w, bool tail)
     return f64 ? 8 : (has_w ? 8 : (tail ? 12 : 16));
 }
 
+// Capped-simplex blocks take at most kCutLaneCap edges on one lane and
+// kCutRmax rows per lane of a segment (their threshold loop keeps bounds and
+// a bracket beside the values; larger classes would spill registers).
+constexpr int kCutLaneCap = 16;
+constexpr int kCutRmax = 8;
+
 enum ItemKind : uint8_t { ITEM_LANE = 0, ITEM_WG = 2 };
 
 struct Item {                // 16 bytes

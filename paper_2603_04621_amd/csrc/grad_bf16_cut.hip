@@ -1,0 +1,6 @@
+// Fused gradient kernel instantiated for uint16_t storage of a and c, variant with capped-simplex blocks.
+#include "grad_impl.hpp"
+
+namespace dl {
+DL_INSTANTIATE_GRAD(uint16_t, true)
+}  // namespace dl

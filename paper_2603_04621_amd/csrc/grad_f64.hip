@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(double)
+DL_INSTANTIATE_GRAD(double, false)
 }  // namespace dl

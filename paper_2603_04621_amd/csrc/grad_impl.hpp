@@ -1341,8 +1341,13 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
     // pipelined runs stop at smaller classes and their one-lane blocks at 16
     // edges (the layout guarantees d <= CAP for S = 1 and R <= RMAX for S > 1)
     constexpr bool W8 = sizeof(VT) == 8;
-    constexpr int RMAX = seg_rmax(W8, HASW, TAIL);
-    constexpr int CAP = lane_cap(W8, HASW, TAIL);
+    // capped-simplex blocks: at most kCutLaneCap edges on one lane and
+    // kCutRmax rows per lane of a segment (the layout guarantees it), which
+    // keeps their threshold loops within the register budget
+    constexpr int RMAX = PJ == 2 ? (seg_rmax(W8, HASW, TAIL) < kCutRmax ? seg_rmax(W8, HASW, TAIL) : kCutRmax)
+                                 : seg_rmax(W8, HASW, TAIL);
+    constexpr int CAP = PJ == 2 ? (lane_cap(W8, HASW, TAIL) < kCutLaneCap ? lane_cap(W8, HASW, TAIL) : kCutLaneCap)
+                                : lane_cap(W8, HASW, TAIL);
     const int cls = lane_class<VT, HASW, TAIL>(it.d, it.lg);
     if (it.lg == 2) {
         if (cls == 8) return lane_run<4, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
@@ -1376,7 +1381,7 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
     }
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
 __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
 {
     if (g.done && *g.done) return;
@@ -1443,9 +1448,15 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
             for (int r = 0; r < rn;) {
                 const Item it = item_at(mine, r);
-                if (it.proj == 1) r = lane_dispatch<VT, CHECK, HASW, TAIL, 1>(g, mine, r, rn, it, s, gamma, ob);
-                else if (it.proj == 2) r = lane_dispatch<VT, CHECK, HASW, TAIL, 2>(g, mine, r, rn, it, s, gamma, ob);
-                else r = lane_dispatch<VT, CHECK, HASW, TAIL, 0>(g, mine, r, rn, it, s, gamma, ob);
+                if (it.proj == 1) {
+                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 1>(g, mine, r, rn, it, s, gamma, ob);
+                } else if (it.proj == 2) {
+                    // capped blocks exist only in problems launched with CUT
+                    if constexpr (CUT) r = lane_dispatch<VT, CHECK, HASW, TAIL, 2>(g, mine, r, rn, it, s, gamma, ob);
+                    else r = rn;
+                } else {
+                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 0>(g, mine, r, rn, it, s, gamma, ob);
+                }
             }
         }
     }
@@ -1454,8 +1465,8 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
         const int d = uni(it.d);
         if (d > 8 * kWG) {
             if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, 1>(g, it, s, gamma, ob);
-            else if (it.proj == 2) wg_block<VT, CHECK, HASW, TAIL, 2>(g, it, s, gamma, ob);
-            else wg_block<VT, CHECK, HASW, TAIL, 0>(g, it, s, gamma, ob);
+            else if (it.proj == 0) wg_block<VT, CHECK, HASW, TAIL, 0>(g, it, s, gamma, ob);
+            else if constexpr (CUT) wg_block<VT, CHECK, HASW, TAIL, 2>(g, it, s, gamma, ob);
             ++i;
             continue;
         }
@@ -1465,9 +1476,13 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
             else i = wg_run<8, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
         } else if (it.proj == 2) {
-            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
-            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
-            else i = wg_run<8, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+            if constexpr (CUT) {
+                if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+                else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+                else i = wg_run<8, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+            } else {
+                i = ch.b1;
+            }
         } else {
             if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
             else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
@@ -1507,71 +1522,71 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     }
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
 __global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
 {
-    grad_body<VT, CHECK, HASW, TAIL>(g, blockIdx.x);
+    grad_body<VT, CHECK, HASW, TAIL, CUT>(g, blockIdx.x);
 }
 
 // batched form: workgroup b runs chunk ct[b].y of problem ct[b].x
-template <typename VT, bool CHECK, bool HASW, bool TAIL>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
 __global__ __launch_bounds__(kWG) void grad_kernel_batch(const GradArgs* __restrict__ tab,
                                                           const int2* __restrict__ ct)
 {
     const int2 e = ct[blockIdx.x];
     const GradArgs g = tab[e.x];
-    grad_body<VT, CHECK, HASW, TAIL>(g, e.y);
+    grad_body<VT, CHECK, HASW, TAIL, CUT>(g, e.y);
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
 static hipError_t launch_grad_t(const GradArgs& a, hipStream_t s)
 {
     const size_t lds = grad_lds_bytes(a.K, a.Kc, CHECK, TAIL);
-    hipLaunchKernelGGL((grad_kernel<VT, CHECK, HASW, TAIL>), dim3(a.nchunks), dim3(kWG), lds, s, a);
+    hipLaunchKernelGGL((grad_kernel<VT, CHECK, HASW, TAIL, CUT>), dim3(a.nchunks), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename VT>
+template <typename VT, bool CUT>
 hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s)
 {
     const bool tail = a.K < a.J;
-#define DL_L(C, W, T) if (check == C && has_w == W && tail == T) return launch_grad_t<VT, C, W, T>(a, s);
+#define DL_L(C, W, T) if (check == C && has_w == W && tail == T) return launch_grad_t<VT, C, W, T, CUT>(a, s);
     DL_L(false, false, false) DL_L(false, false, true) DL_L(false, true, false) DL_L(false, true, true)
     DL_L(true, false, false) DL_L(true, false, true) DL_L(true, true, false) DL_L(true, true, true)
 #undef DL_L
     return hipErrorInvalidValue;
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
 static hipError_t launch_grad_batch_t(const GradArgs* tab, const int2* ct, int nblocks, size_t lds,
                                       hipStream_t s)
 {
-    hipLaunchKernelGGL((grad_kernel_batch<VT, CHECK, HASW, TAIL>), dim3(nblocks), dim3(kWG), lds, s, tab,
+    hipLaunchKernelGGL((grad_kernel_batch<VT, CHECK, HASW, TAIL, CUT>), dim3(nblocks), dim3(kWG), lds, s, tab,
                        ct);
     return hipGetLastError();
 }
 
-template <typename VT>
+template <typename VT, bool CUT>
 hipError_t launch_grad_batch_vt(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
                                 bool has_w, bool tail, hipStream_t s)
 {
 #define DL_L(C, W, T) \
-    if (check == C && has_w == W && tail == T) return launch_grad_batch_t<VT, C, W, T>(tab, ct, nblocks, lds, s);
+    if (check == C && has_w == W && tail == T) return launch_grad_batch_t<VT, C, W, T, CUT>(tab, ct, nblocks, lds, s);
     DL_L(false, false, false) DL_L(false, false, true) DL_L(false, true, false) DL_L(false, true, true)
     DL_L(true, false, false) DL_L(true, false, true) DL_L(true, true, false) DL_L(true, true, true)
 #undef DL_L
     return hipErrorInvalidValue;
 }
 
-template <typename VT>
+template <typename VT, bool CUT>
 hipError_t set_grad_attributes_vt(size_t lds)
 {
     hipError_t e = hipSuccess, r;
 #define DL_A(C, W, T)                                                                        \
-    r = hipFuncSetAttribute((const void*)grad_kernel<VT, C, W, T>,                          \
+    r = hipFuncSetAttribute((const void*)grad_kernel<VT, C, W, T, CUT>,                     \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
     if (r != hipSuccess) e = r;                                                              \
-    r = hipFuncSetAttribute((const void*)grad_kernel_batch<VT, C, W, T>,                    \
+    r = hipFuncSetAttribute((const void*)grad_kernel_batch<VT, C, W, T, CUT>,               \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
     if (r != hipSuccess) e = r;
     DL_A(false, false, false) DL_A(false, false, true) DL_A(false, true, false) DL_A(false, true, true)
@@ -1580,11 +1595,13 @@ hipError_t set_grad_attributes_vt(size_t lds)
     return e;
 }
 
-#define DL_INSTANTIATE_GRAD(VT)                                                              \
-    template hipError_t launch_grad_vt<VT>(const GradArgs&, bool, bool, hipStream_t);     \
-    template hipError_t launch_grad_batch_vt<VT>(const GradArgs*, const int2*, int, size_t, bool, \
-                                                 bool, bool, hipStream_t);                  \
-    template hipError_t set_grad_attributes_vt<VT>(size_t);
+// CUT: the variant that also handles capped-simplex blocks (compiled in its
+// own translation units; problems without such blocks never load its code)
+#define DL_INSTANTIATE_GRAD(VT, CUT)                                                         \
+    template hipError_t launch_grad_vt<VT, CUT>(const GradArgs&, bool, bool, hipStream_t);   \
+    template hipError_t launch_grad_batch_vt<VT, CUT>(const GradArgs*, const int2*, int, size_t, bool, \
+                                                      bool, bool, hipStream_t);              \
+    template hipError_t set_grad_attributes_vt<VT, CUT>(size_t);
 
 
 }  // namespace dl

@@ -14,22 +14,25 @@
 
 namespace dl {
 
-template <typename VT>
+template <typename VT, bool CUT>
 hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s);
-template <typename VT>
+template <typename VT, bool CUT>
 hipError_t set_grad_attributes_vt(size_t lds);
-template <typename VT>
+template <typename VT, bool CUT>
 hipError_t launch_grad_batch_vt(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
                                 bool has_w, bool tail, hipStream_t s);
 
 hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, int storage,
-                             bool check, bool has_w, bool tail, hipStream_t s)
+                             bool check, bool has_w, bool tail, bool cut, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    switch (storage) {
-    case 0: return launch_grad_batch_vt<double>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    case 1: return launch_grad_batch_vt<float>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    default: return launch_grad_batch_vt<uint16_t>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    switch (storage * 2 + (cut ? 1 : 0)) {
+    case 0: return launch_grad_batch_vt<double, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    case 1: return launch_grad_batch_vt<double, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    case 2: return launch_grad_batch_vt<float, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    case 3: return launch_grad_batch_vt<float, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    case 4: return launch_grad_batch_vt<uint16_t, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    default: return launch_grad_batch_vt<uint16_t, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
     }
 }
 
@@ -41,22 +44,28 @@ size_t grad_lds_bytes(int K, int Kc, bool check, bool tail)
     return base + (size_t)K * (sizeof(double) + sizeof(float)) + (size_t)Kc * 2 * sizeof(float);
 }
 
-hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s)
+hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, bool cut, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;
-    switch (storage) {
-    case 0: return launch_grad_vt<double>(a, check, has_w, s);
-    case 1: return launch_grad_vt<float>(a, check, has_w, s);
-    default: return launch_grad_vt<uint16_t>(a, check, has_w, s);
+    switch (storage * 2 + (cut ? 1 : 0)) {
+    case 0: return launch_grad_vt<double, false>(a, check, has_w, s);
+    case 1: return launch_grad_vt<double, true>(a, check, has_w, s);
+    case 2: return launch_grad_vt<float, false>(a, check, has_w, s);
+    case 3: return launch_grad_vt<float, true>(a, check, has_w, s);
+    case 4: return launch_grad_vt<uint16_t, false>(a, check, has_w, s);
+    default: return launch_grad_vt<uint16_t, true>(a, check, has_w, s);
     }
 }
 
 hipError_t set_grad_attributes(size_t lds)
 {
     hipError_t e = hipSuccess, r;
-    if ((r = set_grad_attributes_vt<double>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<float>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<uint16_t>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<double, false>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<double, true>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<float, false>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<float, true>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<uint16_t, false>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<uint16_t, true>(lds)) != hipSuccess) e = r;
     return e;
 }
 

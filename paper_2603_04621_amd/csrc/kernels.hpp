@@ -75,8 +75,9 @@ struct AgdArgs {
 // memory): the three sums of K rows.
 size_t grad_lds_bytes(int K, int Kc, bool check, bool tail);
 
-// storage: 0 f64, 1 f32, 2 bf16 (a, c)
-hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, hipStream_t s);
+// storage: 0 f64, 1 f32, 2 bf16 (a, c); cut: the problem has capped-simplex
+// blocks (the kernel variant that handles them)
+hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, bool cut, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s);
 hipError_t launch_agd(const AgdArgs& a, hipStream_t s);
 hipError_t launch_permute_in(const double* src, const int32_t* orig, int J, double* dst,
@@ -93,7 +94,7 @@ hipError_t set_grad_attributes(size_t max_lds);
 
 // batched forms: tables of per-problem argument blocks in device memory
 hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, int storage,
-                             bool check, bool has_w, bool tail, hipStream_t s);
+                             bool check, bool has_w, bool tail, bool cut, hipStream_t s);
 hipError_t launch_reduce_batch(const ReduceArgs* tab, const int2* rt, int nblocks, hipStream_t s);
 hipError_t launch_agd_batch(const AgdArgs* tab, int count, hipStream_t s);
 hipError_t launch_count_done(const AgdArgs* tab, int count, int* out, hipStream_t s);

@@ -118,7 +118,7 @@ extern "C" dl_status dl_dual_grad_noalloc(dl_problem* p, const double* lambda_de
     g.part = part;
     g.tail = tail;
     g.obj_part = obj_part;
-    if ((e = dl::launch_grad(g, p->storage, check != 0, p->has_w != 0, s)) != hipSuccess)
+    if ((e = dl::launch_grad(g, p->storage, check != 0, p->has_w != 0, p->has_cut != 0, s)) != hipSuccess)
         return dlh::hip_fail(e, "gradient kernel");
     dl::ReduceArgs r = dlh::reduce_args(p, check, 1, lam, nullptr, gamma, nullptr, grad_dev);
     r.part = part;
