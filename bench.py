@@ -351,6 +351,12 @@ def headline(args, I, Problem):
                 storages[st] = {"iter_per_s": args.steps / els, "grad_kernel_ms": kms_s,
                                 "achieved_gbs": sb / (kms_s * 1e-3) / 1e9,
                                 "bytes_per_launch": sb}
+        # deterministic mode (integer per-destination sums): its cost
+        with Problem(inst, storage=args.storage, deterministic=True) as pd:
+            kms_d, cms_d = kernel_times(pd, GAMMA, max(args.steps, 100))
+            storages[args.storage + "_deterministic"] = {
+                "grad_kernel_ms": kms_d, "check_kernel_ms": cms_d,
+                "achieved_gbs": bytes_per / (kms_d * 1e-3) / 1e9, "bytes_per_launch": bytes_per}
         out["storage_variants"] = storages
     return out, inst, lam_eval.cpu().numpy(), gpu_evals
 

@@ -115,6 +115,17 @@ typedef struct {
  *                  for each candidate layout (smaller one-lane blocks, fewer
  *                  rows per lane, two workgroups per compute unit) at lambda =
  *                  0 and keep the fastest; costs a few sample builds at create.
+ *   deterministic  0 (default): the per-destination sums of A x (and of the
+ *                  gap terms) are f32 partials added by LDS atomics in
+ *                  whatever order the waves reach them, so two evaluations
+ *                  agree to rounding (about 1e-7 relative per row), not bit
+ *                  for bit.  1: every term is rounded to a 64-bit fixed-point
+ *                  integer (one power-of-two scale per sum, chosen at create
+ *                  from a bound on the largest row sum, so that no row can
+ *                  overflow 2^60) and added with integer atomics, which are
+ *                  order-independent: dl_dual_grad and dl_solve return the same
+ *                  bits on every run.  Costs LDS (16 instead of 12 bytes per
+ *                  row kept in LDS) and integer conversions per term.
  * The regularizer is gamma/2 sum_e v_e^2 x_e^2 (view (i) of primal scaling). */
 typedef struct {
     dl_storage storage;
@@ -122,11 +133,11 @@ typedef struct {
     int32_t primal_scale;
     const double* v;
     int32_t autotune;
-    int32_t reserved;        /* set to 0 */
+    int32_t deterministic;
 } dl_problem_opts;
 
 /* Fills opts with the defaults (DL_F32, row_normalize = 1, primal_scale = 0,
- * autotune = 0). */
+ * autotune = 0, deterministic = 0). */
 void dl_problem_opts_init(dl_problem_opts* opts);
 
 /* Host-only validation of desc/opts with the rules above; no device is
@@ -326,6 +337,8 @@ typedef struct {
     double anorm2;             /* |A'|^2 of the iteration matrix (see preset): 1
                                   with row normalization and one family, else
                                   max_j |(A D_v^{-1})_j*|^2 (rows are orthogonal)  */
+    int32_t deterministic;     /* 1 when created with deterministic = 1          */
+    int32_t has_capped;        /* 1 when some block is DL_PROJ_CAPPED            */
 } dl_problem_info;
 dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info);
 

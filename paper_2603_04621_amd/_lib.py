@@ -41,7 +41,7 @@ class ProblemDesc(ctypes.Structure):
 
 class ProblemOpts(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int), ("row_normalize", c_i32), ("primal_scale", c_i32),
-                ("v", c_ptr), ("autotune", c_i32), ("reserved", c_i32)]
+                ("v", c_ptr), ("autotune", c_i32), ("deterministic", c_i32)]
 
 
 class Eval(ctypes.Structure):
@@ -70,7 +70,7 @@ class ProblemInfo(ctypes.Structure):
                                      "wg_blocks", "chunks", "lds_rows", "stream_bytes",
                                      "device_bytes")] + [(k, c_i32) for k in (
                     "storage", "has_box", "lane_cap", "seg_rmax", "chunks_per_cu", "tuned")] + [
-                    ("anorm2", c_dbl)]
+                    ("anorm2", c_dbl), ("deterministic", c_i32), ("has_capped", c_i32)]
 
 
 # every symbol include/dualip.h declares

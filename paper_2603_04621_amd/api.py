@@ -56,13 +56,14 @@ class _HostDesc:
 
 
 def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: int = 0, v=None,
-              autotune: bool = False):
+              autotune: bool = False, deterministic: bool = False):
     o = L.ProblemOpts()
     L.lib().dl_problem_opts_init(ctypes.byref(o))
     o.storage = L.STORAGE[storage]
     o.row_normalize = 1 if row_normalize else 0
     o.primal_scale = int(primal_scale)
     o.autotune = 1 if autotune else 0
+    o.deterministic = 1 if deterministic else 0
     keep = None
     if v is not None:
         keep = np.ascontiguousarray(v, dtype=np.float64)
@@ -152,12 +153,12 @@ class Problem:
 
     def __init__(self, inst, storage: str = "f32", row_normalize: bool = True,
                  primal_scale: int = 0, v=None, layout: str = "csc", stream=None,
-                 autotune: bool = False):
+                 autotune: bool = False, deterministic: bool = False):
         import torch
         self.m, self.n = int(inst.m), int(inst.n)
         self.device = torch.device("cuda", torch.cuda.current_device())
         hd = _HostDesc(inst, layout)
-        o, _keep = make_opts(storage, row_normalize, primal_scale, v, autotune)
+        o, _keep = make_opts(storage, row_normalize, primal_scale, v, autotune, deterministic)
         h = ctypes.c_void_p()
         L.check(L.lib().dl_problem_create(ctypes.byref(hd.desc), ctypes.byref(o),
                                           _stream(stream), ctypes.byref(h)), "dl_problem_create")

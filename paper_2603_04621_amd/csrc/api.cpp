@@ -78,7 +78,7 @@ extern "C" void dl_problem_opts_init(dl_problem_opts* o)
     o->primal_scale = 0;
     o->v = nullptr;
     o->autotune = 0;
-    o->reserved = 0;
+    o->deterministic = 0;
 }
 
 extern "C" void dl_solve_opts_init(dl_solve_opts* o)
@@ -191,6 +191,7 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
         if (o->storage < DL_F64 || o->storage > DL_BF16_AC) { set_error("unknown storage %d", (int)o->storage); return DL_ERR_INVALID_ARG; }
         if (o->row_normalize != 0 && o->row_normalize != 1) { set_error("row_normalize must be 0 or 1"); return DL_ERR_INVALID_ARG; }
         if (o->primal_scale < 0 || o->primal_scale > 2) { set_error("primal_scale must be 0, 1 or 2"); return DL_ERR_INVALID_ARG; }
+        if (o->deterministic != 0 && o->deterministic != 1) { set_error("deterministic must be 0 or 1"); return DL_ERR_INVALID_ARG; }
         if (o->primal_scale == 2) {
             if (!o->v) { set_error("primal_scale = 2 needs v"); return DL_ERR_INVALID_ARG; }
             for (int64_t e = 0; e < d->n; ++e)
@@ -449,6 +450,7 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     p->nblocks = d->num_blocks;
     p->storage = opts.storage;
     p->solve_ok = solve_ok;
+    p->det = opts.deterministic;
     p->J = (int)m;
 
     // per column: row and value of its single entry (empty column: row 0, a = 0)
@@ -508,15 +510,18 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     int nch = (int)std::min<int64_t>((int64_t)cus * lc.chunk_mult, std::max<int64_t>(1, (n + 32767) / 32768));
     HostLayout L;
     const size_t max_lds = device_max_lds(p->device);
-    int64_t kmax = ((int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double)) / 12;
+    // bytes of one LDS sum: f32, or a 64-bit integer in deterministic mode
+    const int64_t hes = p->det ? 8 : 4, lds_free = (int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double);
+    int64_t kmax = lds_free / (8 + hes);
     p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
     const bool f64 = opts.storage == DL_F64, tail = p->K < m;
     // check passes: without tail rows the c x and v^2 x^2 sums of the first
     // Kc rows join lam and the a x sums in LDS; with tail rows lam is read
-    // from memory and the three sums of all K rows are in LDS
-    p->Kc = tail ? p->K
-                 : (int)std::max<int64_t>(0, std::min<int64_t>(p->K, ((int64_t)max_lds - 4 * kWaves * 8 -
-                                                                      (int64_t)p->K * 12) / 8));
+    // from memory and the c x and v^2 x^2 sums of the first Kc rows join the
+    // a x sums (all K rows with f32 sums)
+    const int64_t kc = tail ? (lds_free - (int64_t)p->K * hes) / (2 * hes)
+                            : (lds_free - (int64_t)p->K * (8 + hes)) / (2 * hes);
+    p->Kc = (int)std::max<int64_t>(0, std::min<int64_t>(p->K, kc));
     p->lane_cap = std::min(lc.lane_cap, lane_cap(f64, p->has_w != 0, tail));
     p->seg_rmax = std::min(lc.seg_rmax, seg_rmax(f64, p->has_w != 0, tail));
     p->chunk_mult = lc.chunk_mult;
@@ -559,6 +564,31 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
             for (int64_t e = 0; e < n; ++e) box_edges += ebox[e];
     }
     p->stream_bytes = n * (int64_t)(2 * es + 4) + (p->has_box ? 4 * box_edges : 0) + (p->has_w ? 4 * n : 0);
+    if (p->det) {
+        // fixed-point scales of the three per-destination sums: 2^F with F
+        // the largest integer such that a bound on any row's sum (and so on
+        // any partial of it) stays below 2^60 (x_e <= 1 on simplex and capped
+        // blocks, <= u_e on box blocks)
+        std::vector<double> bnd(3 * (size_t)m, 0.0);
+        for (int64_t i = 0; i < d->num_blocks; ++i) {
+            const int pr = d->block_proj[i];
+            for (int64_t e = d->block_off[i]; e < d->block_off[i + 1]; ++e) {
+                const double ue = d->upper ? d->upper[e] : 1.0;
+                const double xm = pr == DL_PROJ_SIMPLEX ? 1.0 : (pr == DL_PROJ_BOX ? ue : std::min(ue, 1.0));
+                const size_t j = (size_t)crow[e];
+                bnd[j] += std::fabs(cval[e]) * xm;
+                bnd[m + j] += std::fabs(d->c[e]) * xm;
+                bnd[2 * m + j] += (p->has_w ? v2[e] : 1.0) * xm * xm;
+            }
+        }
+        for (int q = 0; q < 3; ++q) {
+            double b = 0.0;
+            for (int64_t j = 0; j < m; ++j) b = std::max(b, bnd[(size_t)q * m + j]);
+            b = b > 0.0 ? b * 1.01 : 1.0;
+            const int F = (int)std::floor(60.0 - std::log2(b));
+            p->qs[q] = std::ldexp(1.0, F);
+        }
+    }
 
     // device allocation and upload
 #define ALLOC(ptr, count, what)                                      \
@@ -585,7 +615,8 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     ALLOC(p->b, (size_t)m, "b");
     ALLOC(p->D, (size_t)m, "D");
     ALLOC(p->orig, (size_t)m, "orig");
-    ALLOC(p->part, (size_t)3 * nch * std::max(1, p->K), "partials");
+    // partial sums: f32, or 64-bit integers (two f32 slots) in deterministic mode
+    ALLOC(p->part, (size_t)3 * nch * std::max(1, p->K) * (p->det ? 2 : 1), "partials");
     ALLOC(p->tail, (size_t)3 * m, "tail");
     ALLOC(p->obj_part, (size_t)3 * nch, "objective partials");
     ALLOC(p->blockpart, (size_t)p->nblk2 * kRedStride, "block partials");
@@ -798,6 +829,8 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* i
     info->device_bytes = (int64_t)p->device_bytes;
     info->storage = p->storage;
     info->has_box = p->has_box;
+    info->deterministic = p->det;
+    info->has_capped = p->has_cut;
     info->lane_cap = p->lane_cap;
     info->seg_rmax = p->seg_rmax;
     info->chunks_per_cu = p->chunk_mult;
@@ -836,6 +869,8 @@ GradArgs grad_args(const dl_problem* p, const double* lam, const double* gamma_p
     g.part = p->part;
     g.tail = p->tail;
     g.obj_part = p->obj_part;
+    g.det = p->det;
+    for (int q = 0; q < 3; ++q) g.qs[q] = p->qs[q];
     return g;
 }
 
@@ -865,6 +900,8 @@ ReduceArgs reduce_args(const dl_problem* p, int check, int mode, const double* l
     r.gamma_val = gamma_val;
     r.done = done;
     r.blockpart = p->blockpart;
+    r.det = p->det;
+    for (int q = 0; q < 3; ++q) r.iqs[q] = 1.0 / p->qs[q];
     return r;
 }
 

@@ -84,9 +84,10 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
     }
     // groups by kernel variant (storage, weights, rows beyond LDS: the layout
     // of each problem matches its variant); the largest problems go first
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < n; ++k)
-        by[{probs[k]->storage, probs[k]->has_w, probs[k]->K < probs[k]->J ? 1 : 0, probs[k]->has_cut}].push_back(k);
+        by[{probs[k]->storage, probs[k]->has_w, probs[k]->K < probs[k]->J ? 1 : 0, probs[k]->has_cut,
+            probs[k]->det}].push_back(k);
     std::vector<int2> ct, rb;
     for (auto& kv : by) {
         auto idx = kv.second;
@@ -96,6 +97,7 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
         G.has_w = std::get<1>(kv.first);
         G.tail = std::get<2>(kv.first);
         G.cut = std::get<3>(kv.first);
+        G.det = std::get<4>(kv.first);
         G.lds = 0;
         G.c0 = (int)ct.size();
         // round-robin over problems so long chunks of big problems start early
@@ -103,8 +105,8 @@ dl_status BatchRunner::build(const std::vector<dl_problem*>& probs, const std::v
         for (int k : idx) {
             maxc = std::max(maxc, probs[k]->nchunks);
             const bool tl = probs[k]->K < probs[k]->J;
-            G.lds = std::max({G.lds, grad_lds_bytes(probs[k]->K, probs[k]->Kc, false, tl),
-                              grad_lds_bytes(probs[k]->K, probs[k]->Kc, true, tl)});
+            G.lds = std::max({G.lds, grad_lds_bytes(probs[k]->K, probs[k]->Kc, false, tl, probs[k]->det != 0),
+                              grad_lds_bytes(probs[k]->K, probs[k]->Kc, true, tl, probs[k]->det != 0)});
         }
         for (int c = 0; c < maxc; ++c)
             for (int k : idx)
@@ -157,7 +159,7 @@ hipError_t BatchRunner::enqueue_iteration(int check, hipStream_t s) const
     hipError_t e;
     for (const Group& G : groups_)
         if ((e = launch_grad_batch(gtab_, ctab_ + G.c0, G.nblocks, G.lds, G.storage, check != 0, G.has_w != 0,
-                                   G.tail != 0, G.cut != 0, s)) != hipSuccess)
+                                   G.tail != 0, G.cut != 0, G.det != 0, s)) != hipSuccess)
             return e;
     if ((e = launch_reduce_batch(rtab_[check ? 1 : 0], rbt_, nrb_, s)) != hipSuccess) return e;
     return launch_agd_batch(atab_[check ? 1 : 0], (int)probs_.size(), s);

@@ -1,5 +1,6 @@
 // Batched iteration over several problems: one fused gradient launch per
-// kernel-variant group (storage, primal scale, rows beyond LDS, capped blocks), one reduction launch and one ascent launch
+// kernel-variant group (storage, primal scale, rows beyond LDS, capped
+// blocks, deterministic sums), one reduction launch and one ascent launch
 // per iteration, all driven by per-problem argument tables on the device.
 // Each problem keeps its own chunking, reduction order and FP64 state, so a
 // problem's iterates are the same alone and in a batch.
@@ -29,7 +30,7 @@ public:
 
 private:
     struct Group {
-        int storage, has_w, tail, cut;
+        int storage, has_w, tail, cut, det;
         int c0, nblocks;
         size_t lds;
     };

@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(uint16_t, false)
+DL_INSTANTIATE_GRAD(uint16_t, false, false)
 }  // namespace dl

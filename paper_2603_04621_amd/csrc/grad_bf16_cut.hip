@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(uint16_t, true)
+DL_INSTANTIATE_GRAD(uint16_t, true, false)
 }  // namespace dl

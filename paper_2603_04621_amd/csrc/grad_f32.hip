@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(float, false)
+DL_INSTANTIATE_GRAD(float, false, false)
 }  // namespace dl

@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(float, true)
+DL_INSTANTIATE_GRAD(float, true, false)
 }  // namespace dl

@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(double, false)
+DL_INSTANTIATE_GRAD(double, false, false)
 }  // namespace dl

@@ -2,5 +2,5 @@
 #include "grad_impl.hpp"
 
 namespace dl {
-DL_INSTANTIATE_GRAD(double, true)
+DL_INSTANTIATE_GRAD(double, true, false)
 }  // namespace dl

@@ -194,39 +194,75 @@ __device__ __forceinline__ void gl_add(double* p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// per-destination sums: rows below K in LDS (f32), the rest in FP64 global
-// accumulators (a separate, rarely taken path so the main loop stays lean).
-// Check passes without tail rows keep the c x and v^2 x^2 sums of the first
-// Kc rows in LDS and add the others to the global accumulators.
-template <bool CHECK, bool TAIL>
+// One term of a per-destination sum (plane 0: a x, 1: c x, 2: v^2 x^2).
+// Ordinarily an f32 atomic add into LDS or an FP64 atomic add into the global
+// accumulators, whose result depends on the order the waves add in.  In
+// deterministic mode the term is rounded to a 64-bit fixed-point integer
+// (scale qs[plane], chosen at create so that no row's sum can overflow) and
+// added with an integer atomic: integer addition is associative, so every
+// run gives the same bits.
+// The mode is a compile-time property of the kernel variant: the
+// projection-level templates carry a code PJ whose low two bits are the
+// block's dl_proj and whose bit 2 selects deterministic sums.
+constexpr int pj_proj(int pj) { return pj & 3; }
+constexpr bool pj_det(int pj) { return (pj & 4) != 0; }
+__device__ __forceinline__ unsigned long long fixq(const GradArgs& g, double v, int plane)
+{
+    return (unsigned long long)__double2ll_rn(v * g.qs[plane]);
+}
+template <bool DET>
+__device__ __forceinline__ void lds_term(const GradArgs& g, float* base, int j, double v, int plane)
+{
+    if (DET)
+        __hip_atomic_fetch_add((unsigned long long*)base + j, fixq(g, v, plane), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        lds_add(base + j, (float)v);
+}
+template <bool DET>
+__device__ __forceinline__ void gl_term(const GradArgs& g, double* p, double v, int plane)
+{
+    if (DET)
+        __hip_atomic_fetch_add((unsigned long long*)p, fixq(g, v, plane), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    else
+        gl_add(p, v);
+}
+
+// per-destination sums: rows below K in LDS (f32, or 64-bit integers in
+// deterministic mode), the rest in global accumulators (a separate, rarely
+// taken path so the main loop stays lean).  Check passes keep the c x and
+// v^2 x^2 sums of the first Kc rows in LDS and add the others to the global
+// accumulators.
+template <bool CHECK, bool TAIL, bool DET>
 __device__ __forceinline__ void accum_lds(const Lds& s, const GradArgs& g, int j, double ax, double cx, double q)
 {
-    lds_add(&s.hg[j], (float)ax);
+    lds_term<DET>(g, s.hg, j, ax, 0);
     if (CHECK) {
-        if (TAIL || j < g.Kc) {
-            lds_add(&s.hc[j], (float)cx);
-            lds_add(&s.hq[j], (float)q);
+        if (j < g.Kc) {
+            lds_term<DET>(g, s.hc, j, cx, 1);
+            lds_term<DET>(g, s.hq, j, q, 2);
         } else {
-            gl_add(&g.tail[g.J + j], cx);
-            gl_add(&g.tail[2 * (int64_t)g.J + j], q);
+            gl_term<DET>(g, &g.tail[g.J + j], cx, 1);
+            gl_term<DET>(g, &g.tail[2 * (int64_t)g.J + j], q, 2);
         }
     }
 }
-template <bool CHECK>
+template <bool CHECK, bool DET>
 __device__ __forceinline__ void accum_tail(const GradArgs& g, int j, double ax, double cx, double q)
 {
-    gl_add(&g.tail[j], ax);
+    gl_term<DET>(g, &g.tail[j], ax, 0);
     if (CHECK) {
-        gl_add(&g.tail[g.J + j], cx);
-        gl_add(&g.tail[2 * (int64_t)g.J + j], q);
+        gl_term<DET>(g, &g.tail[g.J + j], cx, 1);
+        gl_term<DET>(g, &g.tail[2 * (int64_t)g.J + j], q, 2);
     }
 }
-template <bool CHECK, bool TAIL>
+template <bool CHECK, bool TAIL, bool DET>
 __device__ __forceinline__ void accum(const Lds& s, const GradArgs& g, int j, double ax, double cx,
                                       double q)
 {
-    if (!TAIL || j < g.K) accum_lds<CHECK, TAIL>(s, g, j, ax, cx, q);
-    else accum_tail<CHECK>(g, j, ax, cx, q);
+    if (!TAIL || j < g.K) accum_lds<CHECK, TAIL, DET>(s, g, j, ax, cx, q);
+    else accum_tail<CHECK, DET>(g, j, ax, cx, q);
 }
 
 // the projected value of one edge given its block threshold: clamp(w (t -
@@ -653,13 +689,14 @@ __device__ __forceinline__ double cut_threshold(const double (&t)[P], const floa
 // per-destination sums
 template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, int P>
 __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, const SegGeo& q,
-                                             double gamma, Obj& ob, const LaneVals<VT, CHECK, PJ != 0, HASW, P>& v)
+                                             double gamma, Obj& ob, const LaneVals<VT, CHECK, pj_proj(PJ) != 0, HASW, P>& v)
 {
-    constexpr bool BOX = PJ != 0;   // per-edge bounds (box and capped blocks)
+    constexpr bool BOX = pj_proj(PJ) != 0;   // per-edge bounds (box and capped blocks)
+    constexpr bool DET = pj_det(PJ);
     const double inv_g = 1.0 / gamma;
     const double* t = v.t;
     double tau = 0.0;
-    if constexpr (PJ == 2) {
+    if constexpr (pj_proj(PJ) == 2) {
         tau = cut_threshold<S, HASW, P>(v.t, v.u, v.w, gamma, inv_g);
     } else if (S > 1) {
         if (!BOX) tau = seg_threshold<S, HASW, P>(v.t, v.w, gamma, inv_g);
@@ -751,7 +788,8 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
     }
 
     // x, objective, per-destination sums of the LDS-resident rows (rows that
-    // are no edge have t = -inf, hence x = 0, and are skipped)
+    // are no edge have t = -inf, hence x = 0, and are skipped); then rows
+    // beyond K (only when some lane of the wave has one)
     bool tail = false;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -763,11 +801,10 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
             ob.oq += q2;
             const double cx = CHECK ? (double)v.c[k] * x : 0.0;
             if (CHECK) ob.oc += cx;
-            if (!TAIL || v.j[k] < g.K) accum_lds<CHECK, TAIL>(s, g, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
+            if (!TAIL || v.j[k] < g.K) accum_lds<CHECK, TAIL, DET>(s, g, v.j[k], (double)opq(v.a[k]) * x, cx, q2);
             else tail = true;
         }
     }
-    // rows beyond K (only when some lane of the wave has one)
     if (TAIL && __builtin_amdgcn_ballot_w64(tail)) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -775,8 +812,8 @@ __device__ __forceinline__ void lane_project(const GradArgs& g, const Lds& s, co
             const double x = xval<BOX>(t[k], w, tau, BOX ? v.u[k] : 0.0f);
             if (x != 0.0 && v.j[k] >= g.K) {
                 const double q2 = HASW ? x * x / (double)v.w[k] : x * x;
-                accum_tail<CHECK>(g, v.j[k], (double)opq(v.a[k]) * x, CHECK ? (double)opq(v.c[k]) * x : 0.0,
-                                  q2);
+                accum_tail<CHECK, DET>(g, v.j[k], (double)opq(v.a[k]) * x, CHECK ? (double)opq(v.c[k]) * x : 0.0,
+                                       q2);
             }
         }
     }
@@ -799,7 +836,7 @@ template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, int P>
 __device__ __forceinline__ void lane_group(const GradArgs& g, const Item& it, const Lds& s,
                                            double gamma, Obj& ob)
 {
-    constexpr bool BOX = PJ != 0;
+    constexpr bool BOX = pj_proj(PJ) != 0;
     static_assert(P <= 32, "lane blocks hold at most 32 edges");
     const SegGeo q = seg_geo<1>(it);
     LaneRaw<VT, BOX, HASW, P> r;
@@ -875,7 +912,7 @@ template <int S, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, int P>
 __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int r, const int rn, const Lds& s,
                                         double gamma, Obj& ob)
 {
-    constexpr bool BOX = PJ != 0;
+    constexpr bool BOX = pj_proj(PJ) != 0;
     static_assert(P <= 16, "pipelined lane runs hold at most 16 rows per group");
     constexpr int LG = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : S == 16 ? 4 : S == 32 ? 5 : 6;
     static_assert((1 << LG) == S, "S is a power of two up to 64");
@@ -891,7 +928,7 @@ __device__ __forceinline__ int lane_run(const GradArgs& g, const Item& mine, int
         SegGeo qn = q;
         if (r + 1 < rn) {
             const Item nx = item_at(mine, r + 1);
-            if (nx.proj == PJ && nx.kind == ITEM_LANE && nx.lg == LG &&
+            if (nx.proj == pj_proj(PJ) && nx.kind == ITEM_LANE && nx.lg == LG &&
                 lane_class<VT, HASW, TAIL>(nx.d, LG) == P) {
                 more = true;
                 qn = seg_geo<S>(nx);
@@ -1072,12 +1109,13 @@ __device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const 
 template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, const Lds& s, double gamma, Obj& ob)
 {
-    constexpr bool BOX = PJ != 0;
+    constexpr bool BOX = pj_proj(PJ) != 0;
+    constexpr bool DET = pj_det(PJ);
     const int d = uni(it.d);
     const int64_t base = uni64(it.base);
     const double inv_g = 1.0 / gamma;
     double tau = 0.0;
-    if constexpr (PJ == 2) tau = wg_cut_threshold_mem<VT, CHECK, HASW, TAIL>(g, s, base, d, gamma, inv_g);
+    if constexpr (pj_proj(PJ) == 2) tau = wg_cut_threshold_mem<VT, CHECK, HASW, TAIL>(g, s, base, d, gamma, inv_g);
     if (!BOX) {
         double s0 = 0.0, mx = -INFINITY;
         for (int e = threadIdx.x; e < d; e += kWG) {
@@ -1139,7 +1177,7 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
             ob.oq += q2;
             const double cx = CHECK ? (double)Val<VT>::ld(C, idx) * x : 0.0;
             if (CHECK) ob.oc += cx;
-            accum<CHECK, TAIL>(s, g, g.dst[idx], a * x, cx, q2);
+            accum<CHECK, TAIL, DET>(s, g, g.dst[idx], a * x, cx, q2);
         }
         if (g.X) g.X[g.perm[idx]] = x;
     }
@@ -1191,13 +1229,14 @@ __device__ __forceinline__ void wg_t(const int d, const LaneRaw<VT, BOX, HASW, R
 
 template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ void wg_project(const GradArgs& g, const Lds& s, const int64_t base, const int d,
-                                           const double gamma, Obj& ob, const LaneVals<VT, CHECK, PJ != 0, HASW, RW>& v)
+                                           const double gamma, Obj& ob, const LaneVals<VT, CHECK, pj_proj(PJ) != 0, HASW, RW>& v)
 {
-    constexpr bool BOX = PJ != 0;
+    constexpr bool BOX = pj_proj(PJ) != 0;
+    constexpr bool DET = pj_det(PJ);
     const double inv_g = 1.0 / gamma;
     const double* t = v.t;
     double tau = 0.0;
-    if constexpr (PJ == 2) tau = wg_cut_threshold<RW, HASW>(v.t, v.u, v.w, gamma, inv_g, s.red);
+    if constexpr (pj_proj(PJ) == 2) tau = wg_cut_threshold<RW, HASW>(v.t, v.u, v.w, gamma, inv_g, s.red);
     if (!BOX) {
         // uniform weights: the two largest t; with the second at most tau_0 =
         // max t - 1/w only the largest is active and tau_0 is the threshold
@@ -1265,7 +1304,7 @@ __device__ __forceinline__ void wg_project(const GradArgs& g, const Lds& s, cons
             ob.oq += q2;
             const double cx = CHECK ? (double)v.c[k] * x : 0.0;
             if (CHECK) ob.oc += cx;
-            accum<CHECK, TAIL>(s, g, v.j[k], (double)v.a[k] * x, cx, q2);
+            accum<CHECK, TAIL, DET>(s, g, v.j[k], (double)v.a[k] * x, cx, q2);
         }
         const int e = k * kWG + (int)threadIdx.x;
         if (g.X && e < d) g.X[g.perm[base + e]] = x;
@@ -1279,7 +1318,7 @@ __device__ __forceinline__ int wg_class(int d) { return d <= 2 * kWG ? 2 : d <= 
 template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
 __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, const Lds& s, double gamma, Obj& ob)
 {
-    constexpr bool BOX = PJ != 0;
+    constexpr bool BOX = pj_proj(PJ) != 0;
     constexpr bool EARLY = !TAIL;   // lam from LDS
     Item it = g.items[i];
     int64_t base = uni64(it.base);
@@ -1294,7 +1333,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
         if (i + 1 < i1) {
             const Item nx = g.items[i + 1];
             const int nd = uni(nx.d);
-            if (nx.proj == PJ && nd <= 8 * kWG && wg_class(nd) == RW) {
+            if (nx.proj == pj_proj(PJ) && nd <= 8 * kWG && wg_class(nd) == RW) {
                 more = true;
                 bn = uni64(nx.base);
                 dn = nd;
@@ -1344,9 +1383,9 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
     // capped-simplex blocks: at most kCutLaneCap edges on one lane and
     // kCutRmax rows per lane of a segment (the layout guarantees it), which
     // keeps their threshold loops within the register budget
-    constexpr int RMAX = PJ == 2 ? (seg_rmax(W8, HASW, TAIL) < kCutRmax ? seg_rmax(W8, HASW, TAIL) : kCutRmax)
+    constexpr int RMAX = pj_proj(PJ) == 2 ? (seg_rmax(W8, HASW, TAIL) < kCutRmax ? seg_rmax(W8, HASW, TAIL) : kCutRmax)
                                  : seg_rmax(W8, HASW, TAIL);
-    constexpr int CAP = PJ == 2 ? (lane_cap(W8, HASW, TAIL) < kCutLaneCap ? lane_cap(W8, HASW, TAIL) : kCutLaneCap)
+    constexpr int CAP = pj_proj(PJ) == 2 ? (lane_cap(W8, HASW, TAIL) < kCutLaneCap ? lane_cap(W8, HASW, TAIL) : kCutLaneCap)
                                 : lane_cap(W8, HASW, TAIL);
     const int cls = lane_class<VT, HASW, TAIL>(it.d, it.lg);
     if (it.lg == 2) {
@@ -1381,7 +1420,7 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
     }
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT, bool DET>
 __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
 {
     if (g.done && *g.done) return;
@@ -1392,7 +1431,10 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     unsigned char* p = smem + 4 * kWaves * sizeof(double);
     const int K = g.K;
     // rows of the c x and v^2 x^2 sums in LDS (check passes)
-    const int KC = CHECK ? (TAIL ? K : g.Kc) : 0;
+    const int KC = CHECK ? g.Kc : 0;
+    // bytes of one LDS sum: f32, or a 64-bit integer in deterministic mode
+    constexpr size_t es = DET ? 8 : 4;
+    constexpr int D4 = DET ? 4 : 0;   // the deterministic bit of the projection codes
     constexpr bool LAM_LDS = !(CHECK && TAIL);
     s.lam = nullptr;
     if (LAM_LDS) {
@@ -1400,11 +1442,11 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
         p += (size_t)K * sizeof(double);
     }
     s.hg = (float*)p;
-    p += (size_t)K * sizeof(float);
+    p += (size_t)K * es;
     s.hc = s.hq = nullptr;
     if (CHECK) {
         s.hc = (float*)p;
-        p += (size_t)KC * sizeof(float);
+        p += (size_t)KC * es;
         s.hq = (float*)p;
     }
     const double gamma = g.gamma_ptr ? *g.gamma_ptr : g.gamma_val;
@@ -1421,12 +1463,21 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             }
             for (; j < K; j += kWG) s.lam[j] = g.lam[j];
         }
-        for (j = threadIdx.x; j < K; j += kWG) s.hg[j] = 0.0f;
-        if (CHECK)
-            for (j = threadIdx.x; j < KC; j += kWG) {
-                s.hc[j] = 0.0f;
-                s.hq[j] = 0.0f;
-            }
+        if constexpr (DET) {
+            for (j = threadIdx.x; j < K; j += kWG) ((unsigned long long*)s.hg)[j] = 0ull;
+            if (CHECK)
+                for (j = threadIdx.x; j < KC; j += kWG) {
+                    ((unsigned long long*)s.hc)[j] = 0ull;
+                    ((unsigned long long*)s.hq)[j] = 0ull;
+                }
+        } else {
+            for (j = threadIdx.x; j < K; j += kWG) s.hg[j] = 0.0f;
+            if (CHECK)
+                for (j = threadIdx.x; j < KC; j += kWG) {
+                    s.hc[j] = 0.0f;
+                    s.hq[j] = 0.0f;
+                }
+        }
     }
     __syncthreads();
 
@@ -1449,13 +1500,13 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             for (int r = 0; r < rn;) {
                 const Item it = item_at(mine, r);
                 if (it.proj == 1) {
-                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 1>(g, mine, r, rn, it, s, gamma, ob);
+                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 1 | D4>(g, mine, r, rn, it, s, gamma, ob);
                 } else if (it.proj == 2) {
                     // capped blocks exist only in problems launched with CUT
-                    if constexpr (CUT) r = lane_dispatch<VT, CHECK, HASW, TAIL, 2>(g, mine, r, rn, it, s, gamma, ob);
+                    if constexpr (CUT) r = lane_dispatch<VT, CHECK, HASW, TAIL, 2 | D4>(g, mine, r, rn, it, s, gamma, ob);
                     else r = rn;
                 } else {
-                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 0>(g, mine, r, rn, it, s, gamma, ob);
+                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 0 | D4>(g, mine, r, rn, it, s, gamma, ob);
                 }
             }
         }
@@ -1464,42 +1515,52 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
         const Item it = g.items[i];
         const int d = uni(it.d);
         if (d > 8 * kWG) {
-            if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, 1>(g, it, s, gamma, ob);
-            else if (it.proj == 0) wg_block<VT, CHECK, HASW, TAIL, 0>(g, it, s, gamma, ob);
-            else if constexpr (CUT) wg_block<VT, CHECK, HASW, TAIL, 2>(g, it, s, gamma, ob);
+            if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, 1 | D4>(g, it, s, gamma, ob);
+            else if (it.proj == 0) wg_block<VT, CHECK, HASW, TAIL, 0 | D4>(g, it, s, gamma, ob);
+            else if constexpr (CUT) wg_block<VT, CHECK, HASW, TAIL, 2 | D4>(g, it, s, gamma, ob);
             ++i;
             continue;
         }
         const int rw = wg_class(d);
         if (it.proj == 1) {
-            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
-            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
-            else i = wg_run<8, VT, CHECK, HASW, TAIL, 1>(g, i, ch.b1, s, gamma, ob);
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 1 | D4>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 1 | D4>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, 1 | D4>(g, i, ch.b1, s, gamma, ob);
         } else if (it.proj == 2) {
             if constexpr (CUT) {
-                if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
-                else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
-                else i = wg_run<8, VT, CHECK, HASW, TAIL, 2>(g, i, ch.b1, s, gamma, ob);
+                if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 2 | D4>(g, i, ch.b1, s, gamma, ob);
+                else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 2 | D4>(g, i, ch.b1, s, gamma, ob);
+                else i = wg_run<8, VT, CHECK, HASW, TAIL, 2 | D4>(g, i, ch.b1, s, gamma, ob);
             } else {
                 i = ch.b1;
             }
         } else {
-            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
-            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
-            else i = wg_run<8, VT, CHECK, HASW, TAIL, 0>(g, i, ch.b1, s, gamma, ob);
+            if (rw == 2) i = wg_run<2, VT, CHECK, HASW, TAIL, 0 | D4>(g, i, ch.b1, s, gamma, ob);
+            else if (rw == 4) i = wg_run<4, VT, CHECK, HASW, TAIL, 0 | D4>(g, i, ch.b1, s, gamma, ob);
+            else i = wg_run<8, VT, CHECK, HASW, TAIL, 0 | D4>(g, i, ch.b1, s, gamma, ob);
         }
     }
     __syncthreads();
 
     // flush: this chunk's row of partial sums, and its objective part
     const int64_t plane = (int64_t)g.nchunks * K;
-    float* row = g.part + (int64_t)chunk * K;
-    for (int j = threadIdx.x; j < K; j += kWG) row[j] = s.hg[j];
-    if (CHECK)
-        for (int j = threadIdx.x; j < KC; j += kWG) {
-            row[plane + j] = s.hc[j];
-            row[2 * plane + j] = s.hq[j];
-        }
+    if constexpr (DET) {
+        unsigned long long* row = (unsigned long long*)g.part + (int64_t)chunk * K;
+        for (int j = threadIdx.x; j < K; j += kWG) row[j] = ((const unsigned long long*)s.hg)[j];
+        if (CHECK)
+            for (int j = threadIdx.x; j < KC; j += kWG) {
+                row[plane + j] = ((const unsigned long long*)s.hc)[j];
+                row[2 * plane + j] = ((const unsigned long long*)s.hq)[j];
+            }
+    } else {
+        float* row = g.part + (int64_t)chunk * K;
+        for (int j = threadIdx.x; j < K; j += kWG) row[j] = s.hg[j];
+        if (CHECK)
+            for (int j = threadIdx.x; j < KC; j += kWG) {
+                row[plane + j] = s.hc[j];
+                row[2 * plane + j] = s.hq[j];
+            }
+    }
     ob.ot = wave_sum(ob.ot);
     ob.oq = wave_sum(ob.oq);
     ob.oc = wave_sum(ob.oc);
@@ -1522,71 +1583,71 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     }
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT, bool DET>
 __global__ __launch_bounds__(kWG) void grad_kernel(GradArgs g)
 {
-    grad_body<VT, CHECK, HASW, TAIL, CUT>(g, blockIdx.x);
+    grad_body<VT, CHECK, HASW, TAIL, CUT, DET>(g, blockIdx.x);
 }
 
 // batched form: workgroup b runs chunk ct[b].y of problem ct[b].x
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT, bool DET>
 __global__ __launch_bounds__(kWG) void grad_kernel_batch(const GradArgs* __restrict__ tab,
                                                           const int2* __restrict__ ct)
 {
     const int2 e = ct[blockIdx.x];
     const GradArgs g = tab[e.x];
-    grad_body<VT, CHECK, HASW, TAIL, CUT>(g, e.y);
+    grad_body<VT, CHECK, HASW, TAIL, CUT, DET>(g, e.y);
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT, bool DET>
 static hipError_t launch_grad_t(const GradArgs& a, hipStream_t s)
 {
-    const size_t lds = grad_lds_bytes(a.K, a.Kc, CHECK, TAIL);
-    hipLaunchKernelGGL((grad_kernel<VT, CHECK, HASW, TAIL, CUT>), dim3(a.nchunks), dim3(kWG), lds, s, a);
+    const size_t lds = grad_lds_bytes(a.K, a.Kc, CHECK, TAIL, DET);
+    hipLaunchKernelGGL((grad_kernel<VT, CHECK, HASW, TAIL, CUT, DET>), dim3(a.nchunks), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename VT, bool CUT>
+template <typename VT, bool CUT, bool DET>
 hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s)
 {
     const bool tail = a.K < a.J;
-#define DL_L(C, W, T) if (check == C && has_w == W && tail == T) return launch_grad_t<VT, C, W, T, CUT>(a, s);
+#define DL_L(C, W, T) if (check == C && has_w == W && tail == T) return launch_grad_t<VT, C, W, T, CUT, DET>(a, s);
     DL_L(false, false, false) DL_L(false, false, true) DL_L(false, true, false) DL_L(false, true, true)
     DL_L(true, false, false) DL_L(true, false, true) DL_L(true, true, false) DL_L(true, true, true)
 #undef DL_L
     return hipErrorInvalidValue;
 }
 
-template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, bool CUT, bool DET>
 static hipError_t launch_grad_batch_t(const GradArgs* tab, const int2* ct, int nblocks, size_t lds,
                                       hipStream_t s)
 {
-    hipLaunchKernelGGL((grad_kernel_batch<VT, CHECK, HASW, TAIL, CUT>), dim3(nblocks), dim3(kWG), lds, s, tab,
+    hipLaunchKernelGGL((grad_kernel_batch<VT, CHECK, HASW, TAIL, CUT, DET>), dim3(nblocks), dim3(kWG), lds, s, tab,
                        ct);
     return hipGetLastError();
 }
 
-template <typename VT, bool CUT>
+template <typename VT, bool CUT, bool DET>
 hipError_t launch_grad_batch_vt(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
                                 bool has_w, bool tail, hipStream_t s)
 {
 #define DL_L(C, W, T) \
-    if (check == C && has_w == W && tail == T) return launch_grad_batch_t<VT, C, W, T, CUT>(tab, ct, nblocks, lds, s);
+    if (check == C && has_w == W && tail == T) return launch_grad_batch_t<VT, C, W, T, CUT, DET>(tab, ct, nblocks, lds, s);
     DL_L(false, false, false) DL_L(false, false, true) DL_L(false, true, false) DL_L(false, true, true)
     DL_L(true, false, false) DL_L(true, false, true) DL_L(true, true, false) DL_L(true, true, true)
 #undef DL_L
     return hipErrorInvalidValue;
 }
 
-template <typename VT, bool CUT>
+template <typename VT, bool CUT, bool DET>
 hipError_t set_grad_attributes_vt(size_t lds)
 {
     hipError_t e = hipSuccess, r;
 #define DL_A(C, W, T)                                                                        \
-    r = hipFuncSetAttribute((const void*)grad_kernel<VT, C, W, T, CUT>,                     \
+    r = hipFuncSetAttribute((const void*)grad_kernel<VT, C, W, T, CUT, DET>,                     \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
     if (r != hipSuccess) e = r;                                                              \
-    r = hipFuncSetAttribute((const void*)grad_kernel_batch<VT, C, W, T, CUT>,               \
+    r = hipFuncSetAttribute((const void*)grad_kernel_batch<VT, C, W, T, CUT, DET>,               \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
     if (r != hipSuccess) e = r;
     DL_A(false, false, false) DL_A(false, false, true) DL_A(false, true, false) DL_A(false, true, true)
@@ -1595,13 +1656,15 @@ hipError_t set_grad_attributes_vt(size_t lds)
     return e;
 }
 
-// CUT: the variant that also handles capped-simplex blocks (compiled in its
-// own translation units; problems without such blocks never load its code)
-#define DL_INSTANTIATE_GRAD(VT, CUT)                                                         \
-    template hipError_t launch_grad_vt<VT, CUT>(const GradArgs&, bool, bool, hipStream_t);   \
-    template hipError_t launch_grad_batch_vt<VT, CUT>(const GradArgs*, const int2*, int, size_t, bool, \
-                                                      bool, bool, hipStream_t);              \
-    template hipError_t set_grad_attributes_vt<VT, CUT>(size_t);
+// CUT: the variant that also handles capped-simplex blocks; DET: the variant
+// with fixed-point integer sums (deterministic mode, instantiated with CUT).
+// Each variant is compiled in its own translation unit, so problems of one
+// kind never carry the code (and register pressure) of the others.
+#define DL_INSTANTIATE_GRAD(VT, CUT, DET)                                                    \
+    template hipError_t launch_grad_vt<VT, CUT, DET>(const GradArgs&, bool, bool, hipStream_t); \
+    template hipError_t launch_grad_batch_vt<VT, CUT, DET>(const GradArgs*, const int2*, int, size_t, bool, \
+                                                           bool, bool, hipStream_t);         \
+    template hipError_t set_grad_attributes_vt<VT, CUT, DET>(size_t);
 
 
 }  // namespace dl

@@ -14,58 +14,79 @@
 
 namespace dl {
 
-template <typename VT, bool CUT>
+template <typename VT, bool CUT, bool DET>
 hipError_t launch_grad_vt(const GradArgs& a, bool check, bool has_w, hipStream_t s);
-template <typename VT, bool CUT>
+template <typename VT, bool CUT, bool DET>
 hipError_t set_grad_attributes_vt(size_t lds);
-template <typename VT, bool CUT>
+template <typename VT, bool CUT, bool DET>
 hipError_t launch_grad_batch_vt(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
                                 bool has_w, bool tail, hipStream_t s);
 
+// kernel variants: plain, with capped-simplex blocks (cut), deterministic
+// (det: integer sums; also handles capped blocks)
+template <typename VT>
+static hipError_t launch_grad_batch_s(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, bool check,
+                                      bool has_w, bool tail, bool cut, bool det, hipStream_t s)
+{
+    if (det) return launch_grad_batch_vt<VT, true, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    if (cut) return launch_grad_batch_vt<VT, true, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    return launch_grad_batch_vt<VT, false, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
+}
+
 hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, int storage,
-                             bool check, bool has_w, bool tail, bool cut, hipStream_t s)
+                             bool check, bool has_w, bool tail, bool cut, bool det, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    switch (storage * 2 + (cut ? 1 : 0)) {
-    case 0: return launch_grad_batch_vt<double, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    case 1: return launch_grad_batch_vt<double, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    case 2: return launch_grad_batch_vt<float, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    case 3: return launch_grad_batch_vt<float, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    case 4: return launch_grad_batch_vt<uint16_t, false>(tab, ct, nblocks, lds, check, has_w, tail, s);
-    default: return launch_grad_batch_vt<uint16_t, true>(tab, ct, nblocks, lds, check, has_w, tail, s);
+    switch (storage) {
+    case 0: return launch_grad_batch_s<double>(tab, ct, nblocks, lds, check, has_w, tail, cut, det, s);
+    case 1: return launch_grad_batch_s<float>(tab, ct, nblocks, lds, check, has_w, tail, cut, det, s);
+    default: return launch_grad_batch_s<uint16_t>(tab, ct, nblocks, lds, check, has_w, tail, cut, det, s);
     }
 }
 
-size_t grad_lds_bytes(int K, int Kc, bool check, bool tail)
+size_t grad_lds_bytes(int K, int Kc, bool check, bool tail, bool det)
 {
     const size_t base = 4 * kWaves * sizeof(double);
-    if (!check) return base + (size_t)K * (sizeof(double) + sizeof(float));
-    if (tail) return base + (size_t)K * 3 * sizeof(float);
-    return base + (size_t)K * (sizeof(double) + sizeof(float)) + (size_t)Kc * 2 * sizeof(float);
+    const size_t es = det ? 8 : 4;
+    if (!check) return base + (size_t)K * (sizeof(double) + es);
+    if (tail) return base + (size_t)K * es + (size_t)Kc * 2 * es;
+    return base + (size_t)K * (sizeof(double) + es) + (size_t)Kc * 2 * es;
+}
+
+template <typename VT>
+static hipError_t launch_grad_s(const GradArgs& a, bool check, bool has_w, bool cut, hipStream_t s)
+{
+    if (a.det) return launch_grad_vt<VT, true, true>(a, check, has_w, s);
+    if (cut) return launch_grad_vt<VT, true, false>(a, check, has_w, s);
+    return launch_grad_vt<VT, false, false>(a, check, has_w, s);
 }
 
 hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, bool cut, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;
-    switch (storage * 2 + (cut ? 1 : 0)) {
-    case 0: return launch_grad_vt<double, false>(a, check, has_w, s);
-    case 1: return launch_grad_vt<double, true>(a, check, has_w, s);
-    case 2: return launch_grad_vt<float, false>(a, check, has_w, s);
-    case 3: return launch_grad_vt<float, true>(a, check, has_w, s);
-    case 4: return launch_grad_vt<uint16_t, false>(a, check, has_w, s);
-    default: return launch_grad_vt<uint16_t, true>(a, check, has_w, s);
+    switch (storage) {
+    case 0: return launch_grad_s<double>(a, check, has_w, cut, s);
+    case 1: return launch_grad_s<float>(a, check, has_w, cut, s);
+    default: return launch_grad_s<uint16_t>(a, check, has_w, cut, s);
     }
+}
+
+template <typename VT>
+static hipError_t set_grad_attributes_s(size_t lds)
+{
+    hipError_t e = hipSuccess, r;
+    if ((r = set_grad_attributes_vt<VT, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<VT, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_vt<VT, true, true>(lds)) != hipSuccess) e = r;
+    return e;
 }
 
 hipError_t set_grad_attributes(size_t lds)
 {
     hipError_t e = hipSuccess, r;
-    if ((r = set_grad_attributes_vt<double, false>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<double, true>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<float, false>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<float, true>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<uint16_t, false>(lds)) != hipSuccess) e = r;
-    if ((r = set_grad_attributes_vt<uint16_t, true>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_s<double>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_s<float>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_attributes_s<uint16_t>(lds)) != hipSuccess) e = r;
     return e;
 }
 
@@ -86,11 +107,17 @@ __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk
     if (j < r.J) {
         const double gamma = r.gamma_ptr ? *r.gamma_ptr : r.gamma_val;
         double ax = 0.0, cj = 0.0, qj = 0.0;
+        // a global accumulator (an integer in deterministic mode), cleared
+        // for the next pass
+        auto take = [&](int64_t idx, int plane) {
+            const double v = r.det ? (double)((const long long*)r.tail)[idx] * r.iqs[plane] : r.tail[idx];
+            r.tail[idx] = 0.0;
+            return v;
+        };
         if (j < r.K) {
             for (int i = 0; i < kRedSlices; ++i) ax += sh[0][i][l];
         } else {
-            ax = r.tail[j];
-            r.tail[j] = 0.0;
+            ax = take(j, 0);
         }
         if (j < r.Kc) {
             if (r.check) {
@@ -100,10 +127,8 @@ __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk
                 }
             }
         } else {
-            cj = r.tail[r.J + j];
-            qj = r.tail[2 * (int64_t)r.J + j];
-            r.tail[r.J + j] = 0.0;
-            r.tail[2 * (int64_t)r.J + j] = 0.0;
+            cj = take(r.J + j, 1);
+            qj = take(2 * (int64_t)r.J + j, 2);
         }
         const double bj = r.b[j];
         const double res = ax - bj;
@@ -145,7 +170,15 @@ __device__ __forceinline__ void reduce_rows(const ReduceArgs& r, const int blk)
     const int64_t plane = (int64_t)r.nchunks * r.K;
     for (int p = 0; p < planes; ++p) {
         double acc = 0.0;
-        if (j < (p == 0 ? r.K : r.Kc)) {
+        if (r.det && j < (p == 0 ? r.K : r.Kc)) {
+            // integer partials: exact sums, converted once per slice
+            const int c0 = (int)(((int64_t)r.nchunks * q) / kRedSlices);
+            const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / kRedSlices);
+            const long long* col = (const long long*)r.part + p * plane + j;
+            long long ia = 0;
+            for (int c = c0; c < c1; ++c) ia += col[(int64_t)c * r.K];
+            acc = (double)ia * r.iqs[p];
+        } else if (j < (p == 0 ? r.K : r.Kc)) {
             const int c0 = (int)(((int64_t)r.nchunks * q) / kRedSlices);
             const int c1 = (int)(((int64_t)r.nchunks * (q + 1)) / kRedSlices);
             const float* col = r.part + p * plane + j;

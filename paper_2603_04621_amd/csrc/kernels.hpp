@@ -27,9 +27,11 @@ struct GradArgs {
     int32_t J, K;            // rows; rows kept in LDS
     int32_t nchunks;
     int32_t Kc;              // check passes: rows whose c x and v^2 x^2 sums stay in LDS
-    float* part;             // [planes][nchunks][K]
-    double* tail;            // [3][J] FP64 accumulators of rows >= K
+    float* part;             // [planes][nchunks][K] (64-bit integers when det)
+    double* tail;            // [3][J] FP64 accumulators of rows beyond LDS (integers when det)
     double* obj_part;        // [nchunks][3]: sum t x, sum v^2 x^2, sum c x (check)
+    int32_t det, pad_det;    // deterministic mode: fixed-point integer sums
+    double qs[3];            // their scales (a x, c x, v^2 x^2)
 };
 
 // Per-destination combination of the chunk partial sums.
@@ -51,6 +53,8 @@ struct ReduceArgs {
     double gamma_val;
     const int32_t* done;
     double* blockpart;       // [gridDim.x][kRedStride]
+    int32_t det, pad_det;    // partials and accumulators are 64-bit integers
+    double iqs[3];           // their inverse scales
 };
 
 struct AgdArgs {
@@ -72,11 +76,13 @@ struct AgdArgs {
 // dynamic LDS of a gradient launch.  Ordinary passes: lam (FP64) and the
 // a x sums of K rows.  Check passes of problems without tail rows: the same
 // plus the c x and v^2 x^2 sums of Kc rows; with tail rows (lam read from
-// memory): the three sums of K rows.
-size_t grad_lds_bytes(int K, int Kc, bool check, bool tail);
+// memory): the a x sums of K rows and the other two of Kc rows.  A sum is an
+// f32, or a 64-bit integer in deterministic mode.
+size_t grad_lds_bytes(int K, int Kc, bool check, bool tail, bool det);
 
 // storage: 0 f64, 1 f32, 2 bf16 (a, c); cut: the problem has capped-simplex
-// blocks (the kernel variant that handles them)
+// blocks (the kernel variant that handles them); a.det selects the
+// deterministic variant
 hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, bool cut, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s);
 hipError_t launch_agd(const AgdArgs& a, hipStream_t s);
@@ -94,7 +100,7 @@ hipError_t set_grad_attributes(size_t max_lds);
 
 // batched forms: tables of per-problem argument blocks in device memory
 hipError_t launch_grad_batch(const GradArgs* tab, const int2* ct, int nblocks, size_t lds, int storage,
-                             bool check, bool has_w, bool tail, bool cut, hipStream_t s);
+                             bool check, bool has_w, bool tail, bool cut, bool det, hipStream_t s);
 hipError_t launch_reduce_batch(const ReduceArgs* tab, const int2* rt, int nblocks, hipStream_t s);
 hipError_t launch_agd_batch(const AgdArgs* tab, int count, hipStream_t s);
 hipError_t launch_count_done(const AgdArgs* tab, int count, int* out, hipStream_t s);

@@ -70,7 +70,7 @@ static size_t noalloc_bytes(const dl_problem* p, int check, size_t* off)
     off[2] = o; o = align256(o + 3 * (size_t)p->nchunks * sizeof(double));                 // obj_part
     off[3] = o; o = align256(o + (size_t)p->nblk2 * dl::kRedStride * sizeof(double));      // blockpart
     off[4] = o; o = align256(o + 8 * sizeof(double));                                      // scalars
-    off[5] = o; o = align256(o + (size_t)(check ? 3 : 1) * p->nchunks * K * sizeof(float));  // partials
+    off[5] = o; o = align256(o + (size_t)(check ? 3 : 1) * p->nchunks * K * (p->det ? 8 : 4));  // partials
     return o;
 }
 

@@ -15,6 +15,8 @@ struct dl_problem {
     int storage = 1;
     int has_box = 0, has_w = 0, solve_ok = 1;
     int has_cut = 0;                   // some block is a capped simplex
+    int det = 0;                       // deterministic mode: fixed-point sums
+    double qs[3] = {1.0, 1.0, 1.0};    // their scales (a x, c x, v^2 x^2)
     double anorm2 = 1.0;               // |A'|^2 of the iteration matrix (presets)
     int J = 0, K = 0;                  // rows; rows resident in LDS
     int Kc = 0;                        // rows of the check-pass c x, v^2 x^2 sums in LDS

@@ -140,7 +140,7 @@ def test_problem_opts_defaults_and_autotune_flag():
     before any device work (so this runs without a GPU)."""
     o, _ = api.make_opts()
     assert o.storage == L.STORAGE["f32"] and o.row_normalize == 1 and o.primal_scale == 0
-    assert o.autotune == 0 and o.reserved == 0
+    assert o.autotune == 0 and o.deterministic == 0
     inst = I.tiny()
     hd = api._HostDesc(inst, "csc")
     o.autotune = 2

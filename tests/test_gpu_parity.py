@@ -41,7 +41,7 @@ def gpu_problem(inst, storage="f32", **kw):
 
 
 def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc", v=None,
-            primal_scale=0, autotune=False):
+            primal_scale=0, autotune=False, deterministic=False):
     """Runs one evaluation on both sides; returns the measured errors."""
     ref_inst = inst.rounded(storage)
     vv = None
@@ -56,7 +56,7 @@ def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc
         v_dev = 1.0 / np.sqrt((1.0 / vv ** 2).astype(np.float32).astype(np.float64))
     ev = O.dual_eval(ref_inst, lam, gamma, v=v_dev)
     with gpu_problem(inst, storage, layout=layout, primal_scale=primal_scale, v=v,
-                     autotune=autotune) as p:
+                     autotune=autotune, deterministic=deterministic) as p:
         grad, x, e = p.dual_grad(torch.from_numpy(lam), gamma, want_x=True, want_eval=True)
         grad = grad.cpu().numpy()
         x = x.cpu().numpy()
@@ -330,6 +330,48 @@ def test_solve_appendix_b_gap_certified(O, dev):
     ev = O.dual_eval(inst.rounded("f32"), lam.cpu().numpy(), r.gamma)
     assert abs(ev.g - r.g) <= 1e-6 * max(1.0, abs(ev.g))
     assert ev.rel_gap <= 1.01e-4
+
+
+def _bitwise_twice(p, lam, gamma):
+    """Two evaluations with x and scalars, and two without: identical bits."""
+    lt = torch.from_numpy(lam)
+    g1, x1, e1 = p.dual_grad(lt, gamma, want_x=True, want_eval=True)
+    g2, x2, e2 = p.dual_grad(lt, gamma, want_x=True, want_eval=True)
+    assert torch.equal(g1, g2) and torch.equal(x1, x2)
+    assert e1 == e2, (e1, e2)
+    g3, _, _ = p.dual_grad(lt, gamma)
+    g4, _, _ = p.dual_grad(lt, gamma)
+    assert torch.equal(g3, g4) and torch.equal(g1, g3)
+
+
+def test_deterministic_mode_bitwise_and_oracle_parity(O, dev):
+    """deterministic = 1: fixed-point integer sums (LDS and global) make
+    repeated evaluations and solves bit-identical, on a problem with rows
+    beyond LDS and box blocks and on one whose gap-check sums are partly in
+    LDS; both still match the oracle to the usual tolerances."""
+    from paper_2603_04621_amd.api import SolveSettings
+    heavy = I.heavy(I=12_000, J=20_000, dmax=4096, capacity="greedy", capped_frac=0.2)
+    large = I.large(I=150_000, J=10_000, capacity="greedy")
+    s = SolveSettings(gamma0=1e-1, gamma_final=1e-2, n_stages=3, stage_iters=50,
+                      tol_rel_gap=-1.0, max_iters=200, check_every=10, preset="natural")
+    for inst, seed in ((heavy, 61), (large, 62)):
+        lam = lam_for(inst, seed, 2.0)
+        compare(O, inst, "f32", lam, 1e-2, deterministic=True)
+        with gpu_problem(inst, "f32", deterministic=True) as p:
+            info = p.info()
+            assert info["deterministic"] == 1
+            _bitwise_twice(p, lam, 1e-2)
+            la, ra = p.solve(s)
+            lb, rb = p.solve(s)
+            assert torch.equal(la, lb) and ra.g == rb.g and ra.rel_gap == rb.rel_gap
+        if inst is heavy:
+            assert info["lds_rows"] < inst.m
+    # the same solve without the flag differs from the deterministic one by
+    # rounding only
+    with gpu_problem(large, "f32") as p:
+        lc, rc = p.solve(s)
+    assert abs(rc.g - ra.g) <= 1e-6 * max(1.0, abs(ra.g))
+    assert lam_close(lc.cpu().numpy(), la.cpu().numpy(), tol=1e-4)
 
 
 def tie_instance(gamma, seed=11):
