@@ -112,6 +112,9 @@ class LP:
 
     @classmethod
     def from_instance(cls, inst, v=None) -> "LP":
+        if hasattr(inst, "colptr"):        # several entries per column (CSC)
+            return cls(inst.m, inst.n, inst.rowidx, inst.val, inst.c, inst.b, inst.block_off,
+                       inst.block_proj, inst.upper, v, colptr=inst.colptr)
         return cls(inst.m, inst.n, inst.dst, inst.a, inst.c, inst.b, inst.block_off,
                    inst.block_proj, inst.upper, v)
 

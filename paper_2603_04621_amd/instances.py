@@ -482,11 +482,112 @@ def appendix_b(I: int = 1_000_000, J: int = 2_000, nu: float = 10.0,
                                          "K": K, "s": sj})
 
 
+@dataclass
+class MultiInstance:
+    """A matching LP with several constraint families (Definition 1) and
+    optionally the global count row of Section 4 (sum_e x_e <= cap): column e
+    (one per edge (i, j)) has an entry in row k J + j of every family k and,
+    with the count row, in row m J.  A is held in CSC form."""
+
+    m: int                       # rows: families * J (+ 1 with the count row)
+    n: int                       # columns = edges
+    colptr: np.ndarray           # int64 [n+1]
+    rowidx: np.ndarray           # int32 [nnz]
+    val: np.ndarray              # float64 [nnz]
+    c: np.ndarray                # float64 [n]
+    b: np.ndarray                # float64 [m]
+    block_off: np.ndarray        # int64 [I+1]
+    block_proj: np.ndarray       # uint8 [I]
+    upper: Optional[np.ndarray]  # float64 [n] or None
+    J: int = 0
+    families: int = 1
+    count_row: bool = False
+    name: str = ""
+    seed: int = 0
+
+    @property
+    def num_blocks(self) -> int:
+        return int(self.block_off.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowidx.shape[0])
+
+    def dense(self) -> np.ndarray:
+        A = np.zeros((self.m, self.n))
+        cols = np.repeat(np.arange(self.n), np.diff(self.colptr))
+        A[self.rowidx, cols] = self.val
+        return A
+
+    def csr(self):
+        """(rowptr int64 [m+1], colidx int32 [nnz], val float64 [nnz])."""
+        cols = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.colptr))
+        order = np.argsort(self.rowidx, kind="stable")
+        rowptr = np.zeros(self.m + 1, dtype=np.int64)
+        np.cumsum(np.bincount(self.rowidx, minlength=self.m), out=rowptr[1:])
+        return rowptr, cols[order].astype(np.int32), self.val[order]
+
+    def rounded(self, storage: str) -> "MultiInstance":
+        """The values a device store of type ``storage`` holds (see Instance.rounded)."""
+        def rnd(v):
+            if storage == "bf16":
+                return _round_bf16(v)
+            if storage == "f32":
+                return v.astype(np.float32).astype(np.float64)
+            return v.copy()
+        up = None if self.upper is None else self.upper.astype(np.float32).astype(np.float64)
+        return MultiInstance(self.m, self.n, self.colptr, self.rowidx, rnd(self.val), rnd(self.c),
+                             self.b, self.block_off, self.block_proj, up, self.J, self.families,
+                             self.count_row, self.name + f"[{storage}]", self.seed)
+
+
+def multi_family(I: int = 100_000, J: int = 1_000, families: int = 2, count_row: bool = True,
+                 seed: int = SEED_BASE + 7, box_frac: float = 0.0, capped_frac: float = 0.0,
+                 count_frac: float = 0.5, zipf: bool = True, dmax: Optional[int] = None
+                 ) -> MultiInstance:
+    """Several matching families on one edge set (Definition 1): sources with
+    1+Poisson(9) distinct destinations (Zipf(1.1) through a seeded permutation,
+    or uniform; dmax > 0 draws degrees uniform in 1..dmax instead), costs
+    c = -LogNormal(0,1), one coefficient per family a^k = LogNormal(0,0.5)
+    drawn independently, greedy-load capacities per family (Appendix B rule
+    applied to that family's coefficients), and with count_row the global
+    count constraint sum_e x_e <= count_frac * (number of sources with edges)."""
+    rng = np.random.default_rng(seed)
+    deg = (1 + rng.poisson(9.0, size=I)) if dmax is None else rng.integers(1, dmax + 1, size=I)
+    deg = np.minimum(deg.astype(np.int64), J)
+    cdf = zipf_cdf(J, 1.1) if zipf else uniform_cdf(J)
+    base = _finish("multi", seed, I, J, deg, rng, cdf, _neg_lognormal, _lognormal_a, 0.3,
+                   box_frac=box_frac, capacity="greedy", seed_key=[seed, 1],
+                   capped_frac=capped_frac)
+    n = base.n
+    coefs = [base.a] + [rng.lognormal(0.0, 0.5, size=n) for _ in range(families - 1)]
+    b = [base.b] + [greedy_capacity(base.dst, coefs[k], base.block_off, J, [seed, 2, k])
+                    for k in range(1, families)]
+    per = families + (1 if count_row else 0)
+    m = families * J + (1 if count_row else 0)
+    rowidx = np.empty((n, per), dtype=np.int32)
+    val = np.empty((n, per))
+    for k in range(families):
+        rowidx[:, k] = k * J + base.dst
+        val[:, k] = coefs[k]
+    bb = np.concatenate(b)
+    if count_row:
+        rowidx[:, families] = families * J
+        val[:, families] = 1.0
+        active = int(np.sum(np.diff(base.block_off) > 0))
+        bb = np.concatenate([bb, [count_frac * active]])
+    colptr = np.arange(0, n * per + 1, per, dtype=np.int64)
+    return MultiInstance(m, n, colptr, rowidx.ravel(), val.ravel(), base.c, bb, base.block_off,
+                         base.block_proj, base.upper, J, families, count_row,
+                         f"multi{families}{'+count' if count_row else ''}", seed)
+
+
 CONFIGS: dict[str, Callable[..., Instance]] = {
     "tiny": tiny,
     "large": large,
     "heavy": heavy,
     "appendix_b": appendix_b,
+    "multi_family": multi_family,
 }
 
 

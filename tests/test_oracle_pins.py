@@ -450,11 +450,11 @@ def qp_optimum(inst, gamma):
     A = inst.dense()
     n = inst.n
     u = inst.upper if inst.upper is not None else np.ones(n)
-    bounds = [(0.0, u[e] if inst.block_proj[np.searchsorted(inst.block_off, e, 'right') - 1] == 1
+    bounds = [(0.0, u[e] if inst.block_proj[np.searchsorted(inst.block_off, e, 'right') - 1] != 0
                else None) for e in range(n)]
     cons = [{"type": "ineq", "fun": lambda x: inst.b - A @ x, "jac": lambda x: -A}]
     for i in range(inst.num_blocks):
-        if inst.block_proj[i] == I.PROJ_SIMPLEX:
+        if inst.block_proj[i] != I.PROJ_BOX:
             lo, hi = int(inst.block_off[i]), int(inst.block_off[i + 1])
             row = np.zeros(n)
             row[lo:hi] = 1.0
@@ -481,7 +481,7 @@ def lp_optimum(inst):
     rows = [A]
     rhs = [inst.b]
     for i in range(inst.num_blocks):
-        if inst.block_proj[i] == I.PROJ_SIMPLEX:
+        if inst.block_proj[i] != I.PROJ_BOX:
             row = np.zeros((1, n))
             row[0, inst.block_off[i]:inst.block_off[i + 1]] = 1.0
             rows.append(row)
@@ -490,7 +490,7 @@ def lp_optimum(inst):
     bounds = []
     for e in range(n):
         i = np.searchsorted(inst.block_off, e, "right") - 1
-        bounds.append((0.0, u[e] if inst.block_proj[i] == 1 else None))
+        bounds.append((0.0, u[e] if inst.block_proj[i] != 0 else None))
     r = so.linprog(inst.c, A_ub=np.vstack(rows), b_ub=np.concatenate(rhs), bounds=bounds,
                    method="highs")
     assert r.status == 0
@@ -832,3 +832,116 @@ def test_momentum_point_is_projected_to_nonnegative(oracle_lib):
         y, lam = np.maximum(0.0, z), ln
     assert clipped                          # the projection of y is exercised
     np.testing.assert_allclose(r.trace[:, 0] - gstar, expect, rtol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# several matching families (Definition 1) and the global count row (Section 4)
+# ---------------------------------------------------------------------------
+
+def brute_block(proj, t, w, u):
+    if proj == I.PROJ_SIMPLEX:
+        return brute_simplex(t, w)
+    if proj == I.PROJ_CAPPED:
+        return brute_capped(t, w, u)
+    return brute_box(t, w, u)
+
+
+@pytest.mark.parametrize("count", [False, True])
+def test_multi_family_products_projection_and_row_scale(oracle_lib, count):
+    """Columns with one entry per family (and one in the count row): x is the
+    blockwise projection of -(A'lam + c)/gamma by brute force on dense A, the
+    gradient is A x - b, g follows Eq.(2); every nonempty row of D A has unit
+    norm (A'A'^T has a unit diagonal, Section 5) and g'(lam') = g(D lam')."""
+    O = oracle_lib
+    inst = I.multi_family(I=30, J=5, families=3 if not count else 2, count_row=count, seed=9,
+                          box_frac=0.3, capped_frac=0.3, dmax=5)
+    A = inst.dense()
+    rng = np.random.default_rng(4)
+    lam = rng.uniform(0, 0.6, size=inst.m)
+    gamma = 0.05
+    ev = O.dual_eval(inst, lam, gamma)
+    t = -(A.T @ lam + inst.c)
+    u = inst.upper if inst.upper is not None else np.ones(inst.n)
+    x = np.concatenate([brute_block(int(inst.block_proj[i]), t[lo:hi], np.full(hi - lo, 1 / gamma),
+                                    u[lo:hi])
+                        for i, (lo, hi) in enumerate(zip(inst.block_off[:-1], inst.block_off[1:]))])
+    np.testing.assert_allclose(ev.x, x, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(ev.grad, A @ x - inst.b, rtol=1e-12, atol=1e-12)
+    g = inst.c @ x + 0.5 * gamma * x @ x + lam @ (A @ x - inst.b)
+    assert ev.g == pytest.approx(g, rel=1e-12)
+    D = O.row_scale(inst)
+    A2 = D[:, None] * A
+    nonempty = np.abs(A).sum(axis=1) > 0
+    np.testing.assert_allclose(np.diag(A2 @ A2.T)[nonempty], 1.0, rtol=1e-13)
+    scaled = I.MultiInstance(inst.m, inst.n, inst.colptr, inst.rowidx,
+                             D[inst.rowidx] * inst.val, inst.c, D * inst.b, inst.block_off,
+                             inst.block_proj, inst.upper, inst.J, inst.families, inst.count_row)
+    e1 = O.dual_eval(scaled, lam, gamma)
+    e0 = O.dual_eval(inst, D * lam, gamma)
+    assert e1.g == pytest.approx(e0.g, rel=1e-12)
+    np.testing.assert_allclose(e1.grad, D * e0.grad, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [80, 81])
+def test_multi_family_gap_brackets_qp_optimum(oracle_lib, seed):
+    """With columns in several rows the restored point scales each edge by
+    the worst ratio of its rows: it must be feasible, so at any lam >= 0
+    g <= P*_gamma <= P (P* from SLSQP on the dense primal QP), and a converged
+    solve reaches P* (1e-7)."""
+    O = oracle_lib
+    inst = I.multi_family(I=10, J=3, families=2, count_row=True, seed=seed, box_frac=0.3,
+                          dmax=3, count_frac=0.4)
+    gamma = 0.05
+    Pstar, _ = qp_optimum(inst, gamma)
+    scale = max(1.0, abs(Pstar))
+    rng = np.random.default_rng(seed)
+    for _ in range(6):
+        lam = rng.exponential(1.0, size=inst.m) * (rng.random(inst.m) < 0.7)
+        ev = O.dual_eval(inst, lam, gamma)
+        assert ev.g <= Pstar + 1e-9 * scale
+        assert ev.P >= Pstar - 1e-9 * scale
+    r = O.solve(inst, O.SolveOpts(gamma0=gamma, gamma_final=gamma, max_iters=40000,
+                                  check_every=10, tol_rel_gap=1e-11, max_step=0.2 * gamma,
+                                  init_step=1e-3 * gamma))
+    assert r.converged
+    assert abs(r.g - Pstar) / scale < 1e-7
+
+
+def test_multi_family_gradient_is_finite_difference_of_g(oracle_lib):
+    O = oracle_lib
+    inst = I.multi_family(I=40, J=6, families=2, count_row=True, seed=12, box_frac=0.3, dmax=6)
+    rng = np.random.default_rng(5)
+    lam = rng.uniform(0.1, 0.8, size=inst.m)
+    gamma = 0.1
+    ev = O.dual_eval(inst, lam, gamma)
+    for h in (1e-6, 1e-7):
+        fd = np.empty(inst.m)
+        for r in range(inst.m):
+            e = np.zeros(inst.m)
+            e[r] = h
+            fd[r] = (O.dual_eval(inst, lam + e, gamma).g - O.dual_eval(inst, lam - e, gamma).g) / (2 * h)
+        np.testing.assert_allclose(fd, ev.grad, rtol=1e-5, atol=1e-6)
+
+
+def test_multi_row_restoration_worked_example(oracle_lib):
+    """A column in two violated rows is scaled by the smaller ratio: the
+    hand-derived example in tests/golden/multi_row_restoration.json."""
+    O = oracle_lib
+    with open(os.path.join(HERE, "golden", "multi_row_restoration.json")) as f:
+        ex = json.load(f)
+    inst = ex["instance"]
+    colptr = [0]
+    rows, vals = [], []
+    for col in inst["columns"]:
+        for r, v in col["entries"]:
+            rows.append(r)
+            vals.append(v)
+        colptr.append(len(rows))
+    lp = O.LP(inst["rows"], 2, np.array(rows, dtype=np.int32), np.array(vals),
+              np.array(inst["c"]), np.array(inst["b"]), np.array([0, 2], dtype=np.int64),
+              np.array([I.PROJ_BOX], dtype=np.uint8), upper=np.ones(2),
+              colptr=np.array(colptr, dtype=np.int64))
+    ev = O.dual_eval(lp, np.array(inst["lambda"]), inst["gamma"])
+    np.testing.assert_allclose(ev.x, ex["x"], rtol=1e-15)
+    assert ev.g == pytest.approx(ex["g"], rel=1e-15)
+    assert ev.P == pytest.approx(ex["P"], rel=1e-15)
