@@ -339,6 +339,8 @@ typedef struct {
                                   max_j |(A D_v^{-1})_j*|^2 (rows are orthogonal)  */
     int32_t deterministic;     /* 1 when created with deterministic = 1          */
     int32_t has_capped;        /* 1 when some block is DL_PROJ_CAPPED            */
+    int32_t col_entries;       /* most entries in one column (1: one family)     */
+    int32_t reserved;
 } dl_problem_info;
 dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info);
 

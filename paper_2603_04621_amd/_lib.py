@@ -70,7 +70,8 @@ class ProblemInfo(ctypes.Structure):
                                      "wg_blocks", "chunks", "lds_rows", "stream_bytes",
                                      "device_bytes")] + [(k, c_i32) for k in (
                     "storage", "has_box", "lane_cap", "seg_rmax", "chunks_per_cu", "tuned")] + [
-                    ("anorm2", c_dbl), ("deterministic", c_i32), ("has_capped", c_i32)]
+                    ("anorm2", c_dbl), ("deterministic", c_i32), ("has_capped", c_i32),
+                    ("col_entries", c_i32), ("reserved", c_i32)]
 
 
 # every symbol include/dualip.h declares

@@ -30,7 +30,13 @@ class _HostDesc:
 
     def __init__(self, inst, layout: str = "csc"):
         self.m, self.n = int(inst.m), int(inst.n)
-        if layout == "csc":
+        multi = hasattr(inst, "colptr")      # several entries per column
+        if layout == "csc" and multi:
+            self.ptr = np.ascontiguousarray(inst.colptr, dtype=np.int64)
+            self.idx = np.ascontiguousarray(inst.rowidx, dtype=np.int32)
+            self.val = np.ascontiguousarray(inst.val, dtype=np.float64)
+            lay = L.DL_CSC
+        elif layout == "csc":
             self.ptr = None
             self.idx = np.ascontiguousarray(inst.dst, dtype=np.int32)
             self.val = np.ascontiguousarray(inst.a, dtype=np.float64)

@@ -136,8 +136,10 @@ static bool finite_all(const double* v, int64_t n)
     return true;
 }
 
-static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* o, int* solve_ok)
+static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* o, int* solve_ok,
+                               int* col_entries = nullptr)
 {
+    int maxk = d && d->n > 0 ? 1 : 0;   // largest number of entries in a column
     if (!d) { set_error("desc is NULL"); return DL_ERR_INVALID_ARG; }
     if (d->m < 1 || d->m >= (int64_t)1 << 28) { set_error("m must be in [1, 2^28)"); return DL_ERR_INVALID_ARG; }
     if (d->n < 0 || d->nnz < 0) { set_error("n and nnz must be >= 0"); return DL_ERR_INVALID_ARG; }
@@ -169,7 +171,8 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
             for (int64_t e = 0; e < d->n; ++e) {
                 const int64_t k = d->ptr[e + 1] - d->ptr[e];
                 if (k < 0) { set_error("CSC ptr decreases at column %lld", (long long)e); return DL_ERR_INVALID_ARG; }
-                if (k > 1) { set_error("column %lld has %lld entries: only one matching family is supported", (long long)e, (long long)k); return DL_ERR_UNSUPPORTED; }
+                if (k > kMfPlanes) { set_error("column %lld has %lld entries: at most %d are supported", (long long)e, (long long)k, kMfPlanes); return DL_ERR_UNSUPPORTED; }
+                maxk = std::max<int>(maxk, (int)k);
             }
         }
         for (int64_t k = 0; k < d->nnz; ++k)
@@ -183,8 +186,8 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
         for (int64_t k = 0; k < d->nnz; ++k) {
             const int32_t e = d->idx[k];
             if (e < 0 || e >= d->n) { set_error("column index %d out of range at %lld", e, (long long)k); return DL_ERR_INVALID_ARG; }
-            if (seen[e]) { set_error("column %d has several entries: only one matching family is supported", e); return DL_ERR_UNSUPPORTED; }
-            seen[e] = 1;
+            if (seen[e] >= kMfPlanes) { set_error("column %d has more than %d entries", e, kMfPlanes); return DL_ERR_UNSUPPORTED; }
+            maxk = std::max<int>(maxk, ++seen[e]);
         }
     }
     if (o) {
@@ -192,6 +195,7 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
         if (o->row_normalize != 0 && o->row_normalize != 1) { set_error("row_normalize must be 0 or 1"); return DL_ERR_INVALID_ARG; }
         if (o->primal_scale < 0 || o->primal_scale > 2) { set_error("primal_scale must be 0, 1 or 2"); return DL_ERR_INVALID_ARG; }
         if (o->deterministic != 0 && o->deterministic != 1) { set_error("deterministic must be 0 or 1"); return DL_ERR_INVALID_ARG; }
+        if (o->deterministic && maxk > 1) { set_error("deterministic mode supports one entry per column only"); return DL_ERR_UNSUPPORTED; }
         if (o->primal_scale == 2) {
             if (!o->v) { set_error("primal_scale = 2 needs v"); return DL_ERR_INVALID_ARG; }
             for (int64_t e = 0; e < d->n; ++e)
@@ -202,12 +206,18 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
     for (int64_t k = 0; k < d->nnz && ok; ++k) ok = d->val[k] >= 0.0;
     for (int64_t j = 0; j < d->m && ok; ++j) ok = d->b[j] >= 0.0;
     if (solve_ok) *solve_ok = ok;
+    if (col_entries) *col_entries = maxk;
     return DL_OK;
 }
 
 extern "C" dl_status dl_problem_validate(const dl_problem_desc* d, const dl_problem_opts* o)
 {
     return validate_impl(d, o, nullptr);
+}
+
+dl_status dlh::validate_desc(const dl_problem_desc* d, const dl_problem_opts* o, int* col_entries)
+{
+    return validate_impl(d, o, nullptr, col_entries);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,9 +444,66 @@ struct LayoutChoice {
 static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& opts, hipStream_t s,
                              LayoutChoice* out);
 
+// |A'|^2 = largest eigenvalue of A'A'^T, A' = D A D_v^{-1} (entries of column e
+// in planes f < count[e] of crow/cval, D in original row order, v2 = v^2 or
+// empty), by power iteration: z <- A'(A'^T z) / |.| from z = 1 until the
+// Rayleigh quotient changes by less than 1e-10 (at most 500 steps).  The
+// quotient approaches the eigenvalue from below; the result is raised by
+// 1e-3 so that a step of 1/L stays on the safe side.
+static double power_anorm2(int64_t m, int64_t n, int nf, const std::vector<int32_t>& crow,
+                           const std::vector<double>& cval, const std::vector<uint8_t>& count,
+                           const std::vector<double>& D, const std::vector<double>& v2)
+{
+    auto coef = [&](int f, int64_t e) {
+        const double a = cval[(size_t)f * n + e] * D[crow[(size_t)f * n + e]];
+        return v2.empty() ? a : a / std::sqrt(v2[e]);
+    };
+    std::vector<double> z((size_t)m, 1.0), y((size_t)n, 0.0), z2((size_t)m, 0.0);
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / (1 << 16)));
+    std::vector<std::vector<double>> part((size_t)nt, std::vector<double>((size_t)m, 0.0));
+    double lam = 0.0;
+    for (int it = 0; it < 500; ++it) {
+        parallel_for(n, 1 << 16, [&](int64_t lo, int64_t hi) {
+            for (int64_t e = lo; e < hi; ++e) {
+                double acc = 0.0;
+                for (int f = 0; f < count[e]; ++f) acc += coef(f, e) * z[crow[(size_t)f * n + e]];
+                y[e] = acc;
+            }
+        });
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                std::vector<double>& pz = part[t];
+                std::fill(pz.begin(), pz.end(), 0.0);
+                const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+                for (int64_t e = lo; e < hi; ++e)
+                    for (int f = 0; f < count[e]; ++f) pz[crow[(size_t)f * n + e]] += coef(f, e) * y[e];
+            });
+        for (auto& x : th) x.join();
+        double zz = 0.0, zm = 0.0;
+        for (int64_t r = 0; r < m; ++r) {
+            double a = 0.0;
+            for (int t = 0; t < nt; ++t) a += part[t][r];
+            z2[r] = a;
+            zz += z[r] * z[r];
+            zm += z[r] * a;
+        }
+        const double q = zz > 0.0 ? zm / zz : 0.0;
+        double nz = 0.0;
+        for (int64_t r = 0; r < m; ++r) nz += z2[r] * z2[r];
+        nz = std::sqrt(nz);
+        if (!(nz > 0.0)) break;
+        for (int64_t r = 0; r < m; ++r) z[r] = z2[r] / nz;
+        const bool done = it > 0 && std::fabs(q - lam) <= 1e-10 * q;
+        lam = q;
+        if (done) break;
+    }
+    return lam > 0.0 ? lam * (1.0 + 1e-3) : 1.0;
+}
+
 // builds and uploads a validated problem with the given layout
 static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& opts, int solve_ok,
-                             const LayoutChoice& lc, hipStream_t s, dl_problem** out)
+                             const LayoutChoice& lc, hipStream_t s, dl_problem** out, int col_entries = 1)
 {
     dl_status st = DL_OK;
     const int64_t m = d->m, n = d->n;
@@ -453,24 +520,45 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     p->det = opts.deterministic;
     p->J = (int)m;
 
-    // per column: row and value of its single entry (empty column: row 0, a = 0)
-    std::vector<int32_t> crow((size_t)n, 0);
-    std::vector<double> cval((size_t)n, 0.0);
+    // per column: rows and values of its entries, entry f in plane f
+    // (crow[f n + e]); an empty column and missing entries: row 0, a = 0
+    const int nf = std::max(1, col_entries);
+    p->nf = nf;
+    std::vector<int32_t> crow((size_t)n * nf, 0);
+    std::vector<double> cval((size_t)n * nf, 0.0);
+    std::vector<uint8_t> ccount(nf > 1 ? (size_t)n : 0, 0);
     if (d->layout == DL_CSC) {
         for (int64_t e = 0; e < n; ++e) {
             const int64_t lo = d->ptr ? d->ptr[e] : e, hi = d->ptr ? d->ptr[e + 1] : e + 1;
-            if (hi > lo) { crow[e] = d->idx[lo]; cval[e] = d->val[lo]; }
+            for (int64_t k = lo; k < hi; ++k) {
+                crow[(size_t)(k - lo) * n + e] = d->idx[k];
+                cval[(size_t)(k - lo) * n + e] = d->val[k];
+            }
+            if (nf > 1) ccount[e] = (uint8_t)(hi - lo);
         }
     } else {
+        std::vector<uint8_t> cnt((size_t)n, 0);
         for (int64_t j = 0; j < m; ++j)
-            for (int64_t k = d->ptr[j]; k < d->ptr[j + 1]; ++k) { crow[d->idx[k]] = (int32_t)j; cval[d->idx[k]] = d->val[k]; }
+            for (int64_t k = d->ptr[j]; k < d->ptr[j + 1]; ++k) {
+                const int32_t e = d->idx[k];
+                const size_t f = cnt[e]++;
+                crow[f * n + e] = (int32_t)j;
+                cval[f * n + e] = d->val[k];
+            }
+        if (nf > 1) ccount = cnt;
     }
     // primal scale v (regularizer gamma/2 v^2 x^2) and Jacobi row scale of A D_v^{-1}
     std::vector<double> v2;
     if (opts.primal_scale != 0) {
         v2.resize((size_t)n);
         for (int64_t e = 0; e < n; ++e) {
-            double v = opts.primal_scale == 1 ? std::fabs(cval[e]) : opts.v[e];
+            double v = opts.v ? opts.v[e] : 0.0;
+            if (opts.primal_scale == 1) {
+                // column norm |A_{:,e}|_2 over the column's entries
+                double c2 = 0.0;
+                for (int f = 0; f < nf; ++f) c2 += cval[(size_t)f * n + e] * cval[(size_t)f * n + e];
+                v = std::sqrt(c2);
+            }
             if (!(v > 0.0)) v = 1.0;
             v2[e] = v * v;
         }
@@ -482,6 +570,12 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         const double z = cval[e];
         r2[crow[e]] += p->has_w ? z * z / v2[e] : z * z;
         rdeg[crow[e]] += 1;
+        for (int f = 1; f < nf && f < ccount[e]; ++f) {
+            const double zf = cval[(size_t)f * n + e];
+            const int32_t rf = crow[(size_t)f * n + e];
+            r2[rf] += p->has_w ? zf * zf / v2[e] : zf * zf;
+            rdeg[rf] += 1;
+        }
     }
     // relabel rows by descending degree (ties by index): hot rows first
     std::vector<int32_t> orig((size_t)m), newid((size_t)m);
@@ -495,8 +589,13 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         Dv[j] = (opts.row_normalize && r2[o] > 0.0) ? 1.0 / std::sqrt(r2[o]) : 1.0;
     }
     // one family: A D_v^{-1} has orthogonal rows, so |A'|^2 is the largest
-    // squared row norm (1 after row normalization, empty rows aside)
-    {
+    // squared row norm (1 after row normalization, empty rows aside);
+    // several entries per column: power iteration on A'A'^T
+    if (nf > 1) {
+        std::vector<double> Do((size_t)m);
+        for (int64_t j = 0; j < m; ++j) Do[orig[j]] = Dv[j];
+        p->anorm2 = power_anorm2(m, n, nf, crow, cval, ccount, Do, v2);
+    } else {
         double mx = 0.0;
         for (int64_t j = 0; j < m; ++j) mx = std::max(mx, opts.row_normalize ? (r2[j] > 0.0 ? 1.0 : 0.0) : r2[j]);
         p->anorm2 = mx > 0.0 ? mx : 1.0;
@@ -524,6 +623,13 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     p->Kc = (int)std::max<int64_t>(0, std::min<int64_t>(p->K, kc));
     p->lane_cap = std::min(lc.lane_cap, lane_cap(f64, p->has_w != 0, tail));
     p->seg_rmax = std::min(lc.seg_rmax, seg_rmax(f64, p->has_w != 0, tail));
+    if (nf > 1) {
+        // multi-entry columns: no per-row c x, v^2 x^2 sums (the gap's
+        // restoration is a pass of its own) and smaller lane classes
+        p->Kc = 0;
+        p->lane_cap = std::min(p->lane_cap, kMfLaneCap);
+        p->seg_rmax = std::min(p->seg_rmax, kMfRmax);
+    }
     p->chunk_mult = lc.chunk_mult;
     p->tuned = lc.tuned;
     build_items(d, nch, p->lane_cap, p->seg_rmax, L);
@@ -538,6 +644,9 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     const size_t es = opts.storage == DL_F64 ? 8 : (opts.storage == DL_F32 ? 4 : 2);
     std::vector<unsigned char> Ah((size_t)n * es), Ch((size_t)n * es);
     std::vector<int32_t> dsth((size_t)n);
+    // planes 1..nf-1 of multi-entry columns (coefficients, internal rows)
+    std::vector<unsigned char> A2h((size_t)(nf - 1) * n * es);
+    std::vector<int32_t> dst2h((size_t)(nf - 1) * n);
     std::vector<float> Uh(p->has_box ? (size_t)n : 0), IVh(p->has_w ? (size_t)n : 0);
     int64_t box_edges = 0;
     {
@@ -556,6 +665,14 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
                 else if (opts.storage == DL_F32) { ((float*)Ah.data())[q] = (float)a; ((float*)Ch.data())[q] = (float)c; }
                 else { ((uint16_t*)Ah.data())[q] = to_bf16(a); ((uint16_t*)Ch.data())[q] = to_bf16(c); }
                 dsth[q] = newid[crow[e]];
+                for (int f = 1; f < nf; ++f) {
+                    const size_t qf = (size_t)(f - 1) * n + q;
+                    const double af = cval[(size_t)f * n + e];
+                    if (opts.storage == DL_F64) ((double*)A2h.data())[qf] = af;
+                    else if (opts.storage == DL_F32) ((float*)A2h.data())[qf] = (float)af;
+                    else ((uint16_t*)A2h.data())[qf] = to_bf16(af);
+                    dst2h[qf] = newid[crow[(size_t)f * n + e]];
+                }
                 if (p->has_box) Uh[q] = (float)(d->upper ? d->upper[e] : 1.0);
                 if (p->has_w) IVh[q] = (float)(1.0 / v2[e]);
             }
@@ -563,7 +680,7 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
         if (p->has_box)
             for (int64_t e = 0; e < n; ++e) box_edges += ebox[e];
     }
-    p->stream_bytes = n * (int64_t)(2 * es + 4) + (p->has_box ? 4 * box_edges : 0) + (p->has_w ? 4 * n : 0);
+    p->stream_bytes = n * (int64_t)(es + nf * (es + 4)) + (p->has_box ? 4 * box_edges : 0) + (p->has_w ? 4 * n : 0);
     if (p->det) {
         // fixed-point scales of the three per-destination sums: 2^F with F
         // the largest integer such that a bound on any row's sum (and so on
@@ -622,6 +739,16 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     ALLOC(p->blockpart, (size_t)p->nblk2 * kRedStride, "block partials");
     ALLOC(p->lam_int, (size_t)m, "lambda");
     ALLOC(p->eval6, 8, "eval");
+    if (nf > 1) {
+        for (int f = 1; f < nf; ++f) {
+            unsigned char* Af;
+            ALLOC(Af, (size_t)n * es, "coefficient plane");
+            p->A2[f - 1] = Af;
+            ALLOC(p->dst2[f - 1], (size_t)n, "row plane");
+        }
+        ALLOC(p->srow, (size_t)m, "row ratios");
+        ALLOC(p->corr_part, (size_t)nch, "restoration partials");
+    }
     ALLOC(p->lam, (size_t)m, "lam");
     ALLOC(p->y, (size_t)m, "y");
     ALLOC(p->yp, (size_t)m, "y_prev");
@@ -632,6 +759,10 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     UP(p->A, Ah.data(), Ah.size(), "upload a");
     UP(p->C, Ch.data(), Ch.size(), "upload c");
     UP(p->dst, dsth.data(), dsth.size() * 4, "upload dst");
+    for (int f = 1; f < nf; ++f) {
+        UP(p->A2[f - 1], A2h.data() + (size_t)(f - 1) * n * es, (size_t)n * es, "upload plane");
+        UP(p->dst2[f - 1], dst2h.data() + (size_t)(f - 1) * n, (size_t)n * 4, "upload plane rows");
+    }
     if (p->has_box) UP(p->U, Uh.data(), Uh.size() * 4, "upload upper");
     if (p->has_w) UP(p->IV, IVh.data(), IVh.size() * 4, "upload scale");
     UP(p->perm, L.src.data(), L.src.size() * 8, "upload perm");
@@ -771,16 +902,18 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     dl_problem_opts_init(&opts);
     if (opts_in) opts = *opts_in;
     if (opts.autotune != 0 && opts.autotune != 1) { set_error("autotune must be 0 or 1"); return DL_ERR_INVALID_ARG; }
-    int solve_ok = 1;
-    dl_status st = validate_impl(d, &opts, &solve_ok);
+    int solve_ok = 1, col_entries = 1;
+    dl_status st = validate_impl(d, &opts, &solve_ok, &col_entries);
     if (st != DL_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     LayoutChoice lc;
-    if (opts.autotune) {
+    // (multi-entry columns keep the default layout: the tuner samples one
+    // entry per column)
+    if (opts.autotune && col_entries <= 1) {
         st = tune_layout(d, opts, s, &lc);
         if (st != DL_OK) return st;
     }
-    return create_with(d, opts, solve_ok, lc, s, out);
+    return create_with(d, opts, solve_ok, lc, s, out, col_entries);
 }
 
 extern "C" dl_status dl_problem_destroy(dl_problem* p)
@@ -831,6 +964,8 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* i
     info->has_box = p->has_box;
     info->deterministic = p->det;
     info->has_capped = p->has_cut;
+    info->col_entries = p->nf;
+    info->reserved = 0;
     info->lane_cap = p->lane_cap;
     info->seg_rmax = p->seg_rmax;
     info->chunks_per_cu = p->chunk_mult;
@@ -871,6 +1006,14 @@ GradArgs grad_args(const dl_problem* p, const double* lam, const double* gamma_p
     g.obj_part = p->obj_part;
     g.det = p->det;
     for (int q = 0; q < 3; ++q) g.qs[q] = p->qs[q];
+    g.nf = p->nf;
+    for (int f = 0; f + 1 < kMfPlanes; ++f) {
+        g.A2[f] = p->A2[f];
+        g.dst2[f] = p->dst2[f];
+    }
+    g.restore = 0;
+    g.srow = p->srow;
+    g.corr_part = p->corr_part;
     return g;
 }
 
@@ -902,6 +1045,7 @@ ReduceArgs reduce_args(const dl_problem* p, int check, int mode, const double* l
     r.blockpart = p->blockpart;
     r.det = p->det;
     for (int q = 0; q < 3; ++q) r.iqs[q] = 1.0 / p->qs[q];
+    r.srow = check && p->nf > 1 ? p->srow : nullptr;
     return r;
 }
 
@@ -925,6 +1069,7 @@ AgdArgs agd_args(const dl_problem* p, const SolveParams& prm, int check, double*
     a.lam_eval = p->lam_eval;
     a.D = p->D;
     a.trace = trace;
+    a.corr_part = p->nf > 1 ? p->corr_part : nullptr;
     return a;
 }
 
@@ -941,6 +1086,12 @@ hipError_t enqueue_iteration(dl_problem* p, const SolveParams& prm, int check, d
     ReduceArgs r = reduce_args(p, check, 0, p->lam_eval, gptr, 0.0, done, nullptr);
     AgdArgs a = agd_args(p, prm, check, trace);
     if ((e = launch_reduce(r, p->nblk2, s)) != hipSuccess) return e;
+    if (check && p->nf > 1) {
+        // the gap's restoration over each edge's rows (multi-entry columns)
+        GradArgs gr = g;
+        gr.restore = 1;
+        if ((e = launch_grad(gr, p->storage, false, p->has_w != 0, p->has_cut != 0, s)) != hipSuccess) return e;
+    }
     return launch_agd(a, s);
 }
 
@@ -1004,7 +1155,13 @@ extern "C" dl_status dl_dual_grad(dl_problem* p, const double* lambda_dev, doubl
     ReduceArgs r = dlh::reduce_args(p, check, 1, p->lam_int, nullptr, gamma, nullptr, grad_dev);
     HIP_TRY(launch_reduce(r, p->nblk2, s), "reduce kernel");
     if (eval_host) {
-        HIP_TRY(launch_eval_finish(p->obj_part, p->nchunks, p->blockpart, p->nblk2, 1, gamma, p->eval6, s),
+        if (p->nf > 1) {
+            GradArgs gr = dlh::grad_args(p, p->lam_int, nullptr, gamma, nullptr, nullptr);
+            gr.restore = 1;
+            HIP_TRY(launch_grad(gr, p->storage, false, p->has_w != 0, p->has_cut != 0, s), "restoration pass");
+        }
+        HIP_TRY(launch_eval_finish(p->obj_part, p->nchunks, p->blockpart, p->nblk2, 1, gamma, p->eval6, s,
+                                   p->nf > 1 ? p->corr_part : nullptr),
                 "evaluation kernel");
         double h[8];
         HIP_TRY(hipMemcpyAsync(h, p->eval6, 6 * sizeof(double), hipMemcpyDeviceToHost, s), "copy scalars");

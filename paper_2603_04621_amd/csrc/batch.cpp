@@ -218,6 +218,7 @@ extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, con
     for (int k = 0; k < count; ++k) {
         if (!ps[k] || !lambdas[k]) { set_error("NULL problem or lambda at %d", k); return DL_ERR_INVALID_ARG; }
         if (!ps[k]->solve_ok) { set_error("problem %d has a < 0 or b < 0", k); return DL_ERR_UNSUPPORTED; }
+        if (ps[k]->nf > 1) { set_error("problem %d has columns with several entries: batched solves take one entry per column", k); return DL_ERR_UNSUPPORTED; }
         for (int q = 0; q < k; ++q)
             if (ps[q] == ps[k]) { set_error("problem %d appears twice in the batch", k); return DL_ERR_INVALID_ARG; }
     }

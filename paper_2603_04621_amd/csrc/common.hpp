@@ -59,6 +59,14 @@ constexpr int seg_rmax(bool f64, bool has_w, bool tail)
 constexpr int kCutLaneCap = 16;
 constexpr int kCutRmax = 8;
 
+// Columns with several entries (several matching families, dense rows): at
+// most kMfPlanes entries per column; blocks take at most kMfLaneCap edges on
+// one lane and kMfRmax rows per lane (the entries multiply the registers per
+// edge).
+constexpr int kMfPlanes = 4;
+constexpr int kMfLaneCap = 8;
+constexpr int kMfRmax = 8;
+
 enum ItemKind : uint8_t { ITEM_LANE = 0, ITEM_WG = 2 };
 
 struct Item {                // 16 bytes

@@ -1052,20 +1052,21 @@ __device__ __forceinline__ double wg_cut_threshold(const double (&t)[RW], const 
 }
 
 // the same for WG blocks beyond the register form: t recomputed from memory
-// on every pass (the block stays in L2 between passes)
-template <typename VT, bool CHECK, bool HASW, bool TAIL>
-__device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const Lds& s, const int64_t base,
-                                                      const int d, const double gamma, const double inv_g)
+// on every pass (the block stays in L2 between passes); et(idx, w) returns
+// t of stream position idx and sets w = 1/(gamma v^2)
+template <bool HASW, typename ET>
+__device__ __forceinline__ double wg_cut_threshold_fn(const GradArgs& g, ET et, const int64_t base, const int d,
+                                                     const double gamma, double* red)
 {
     double s0 = 0.0, z0 = 0.0, z1 = 0.0;
     for (int e = threadIdx.x; e < d; e += kWG) {
         double w;
-        const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+        const double t = et(base + e, w);
         const double uu = (double)g.U[base + e];
         const double z = w * t;
         s0 += z > 0.0 ? (z < uu ? z : uu) : 0.0;
     }
-    wg_sum3d(s0, z0, z1, s.red);
+    wg_sum3d(s0, z0, z1, red);
     if (!(s0 > 1.0)) return 0.0;
     double lo = 0.0, hi = INFINITY, tau = 0.0;
 #pragma unroll 1
@@ -1073,7 +1074,7 @@ __device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const 
         double sw = 0.0, swt = 0.0, su = 0.0;
         for (int e = threadIdx.x; e < d; e += kWG) {
             double w;
-            const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+            const double t = et(base + e, w);
             const float uk = g.U[base + e];
             const float wk = HASW ? g.IV[base + e] : 1.0f;
             const bool fr = cut_free<HASW>(t, uk, wk, gamma, lo, hi);
@@ -1082,12 +1083,12 @@ __device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const 
             swt += fr ? w * t : 0.0;
             su += up ? (double)uk : 0.0;
         }
-        wg_sum3d(sw, swt, su, s.red);
+        wg_sum3d(sw, swt, su, red);
         const double tf = sw > 0.0 ? (swt + su - 1.0) / sw : lo;
         double dn = 0.0, dup = 0.0, nv = 0.0;
         for (int e = threadIdx.x; e < d; e += kWG) {
             double w;
-            const double t = edge_t<VT, CHECK, HASW, TAIL>(g, s, base + e, w, inv_g);
+            const double t = et(base + e, w);
             const float uk = g.U[base + e];
             const float wk = HASW ? g.IV[base + e] : 1.0f;
             const bool fr = cut_free<HASW>(t, uk, wk, gamma, lo, hi);
@@ -1097,13 +1098,20 @@ __device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const 
             dup += above ? z - (double)uk : 0.0;
             nv += (below || above) ? 1.0 : 0.0;
         }
-        wg_sum3d(dn, dup, nv, s.red);
+        wg_sum3d(dn, dup, nv, red);
         tau = tf;
         if (nv == 0.0 || !(sw > 0.0)) break;
         if (dn >= dup) lo = fmax(lo, tf);
         else hi = fmin(hi, tf);
     }
     return tau;
+}
+template <typename VT, bool CHECK, bool HASW, bool TAIL>
+__device__ __forceinline__ double wg_cut_threshold_mem(const GradArgs& g, const Lds& s, const int64_t base,
+                                                      const int d, const double gamma, const double inv_g)
+{
+    auto et = [&](int64_t idx, double& w) { return edge_t<VT, CHECK, HASW, TAIL>(g, s, idx, w, inv_g); };
+    return wg_cut_threshold_fn<HASW>(g, et, base, d, gamma, s.red);
 }
 
 template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>

@@ -61,9 +61,27 @@ static hipError_t launch_grad_s(const GradArgs& a, bool check, bool has_w, bool 
     return launch_grad_vt<VT, false, false>(a, check, has_w, s);
 }
 
+template <typename VT>
+hipError_t launch_grad_mf_vt(const GradArgs& a, bool has_w, hipStream_t s);
+template <typename VT>
+hipError_t set_grad_mf_attributes_vt(size_t lds);
+
+hipError_t launch_grad_mf(const GradArgs& a, int storage, bool has_w, hipStream_t s)
+{
+    if (a.nchunks <= 0) return hipSuccess;
+    switch (storage) {
+    case 0: return launch_grad_mf_vt<double>(a, has_w, s);
+    case 1: return launch_grad_mf_vt<float>(a, has_w, s);
+    default: return launch_grad_mf_vt<uint16_t>(a, has_w, s);
+    }
+}
+
 hipError_t launch_grad(const GradArgs& a, int storage, bool check, bool has_w, bool cut, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;
+    // columns with several entries: the multi-entry kernel (it keeps the
+    // c x sum on every pass; the gap's restoration is a pass of its own)
+    if (a.nf > 1) return launch_grad_mf(a, storage, has_w, s);
     switch (storage) {
     case 0: return launch_grad_s<double>(a, check, has_w, cut, s);
     case 1: return launch_grad_s<float>(a, check, has_w, cut, s);
@@ -87,6 +105,9 @@ hipError_t set_grad_attributes(size_t lds)
     if ((r = set_grad_attributes_s<double>(lds)) != hipSuccess) e = r;
     if ((r = set_grad_attributes_s<float>(lds)) != hipSuccess) e = r;
     if ((r = set_grad_attributes_s<uint16_t>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_mf_attributes_vt<double>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_mf_attributes_vt<float>(lds)) != hipSuccess) e = r;
+    if ((r = set_grad_mf_attributes_vt<uint16_t>(lds)) != hipSuccess) e = r;
     return e;
 }
 
@@ -146,6 +167,7 @@ __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk
         }
         if (r.check) {
             const double sj = ax > bj ? bj / ax : 1.0;
+            if (r.srow) r.srow[j] = sj;
             S[4] = (sj - 1.0) * cj + 0.5 * gamma * (sj * sj - 1.0) * qj;
             S[5] = res > 0.0 ? res : 0.0;
         }
@@ -243,14 +265,17 @@ constexpr int kSW = kScalarThreads / 64;
 
 __device__ __forceinline__ void reduce_scalars(const double* obj_part, int nchunks, const double* bp,
                                                int nblk, double* out /*[9] shared*/,
-                                               double* red /*[9*kSW] shared*/)
+                                               double* red /*[9*kSW] shared*/, const double* corr)
 {
-    // out: 0 sum t x, 1 sum v^2 x^2, 2 sum c x, 3..7 block sums 0..4, 8 max of block value 5
+    // out: 0 sum t x, 1 sum v^2 x^2, 2 sum c x, 3..7 block sums 0..4 (7: the
+    // gap's restoration correction, plus the per-chunk corrections of a
+    // restoration pass when corr is given), 8 max of block value 5
     double v[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < nchunks; i += blockDim.x) {
         v[0] += obj_part[3 * i];
         v[1] += obj_part[3 * i + 1];
         v[2] += obj_part[3 * i + 2];
+        if (corr) v[7] += corr[i];
     }
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
 #pragma unroll
@@ -278,11 +303,12 @@ __device__ __forceinline__ void reduce_scalars(const double* obj_part, int nchun
 // evaluation scalars: g, c'x, gamma/2 |D_v x|^2, P, rel_gap, max_infeas
 __global__ __launch_bounds__(kScalarThreads) void eval_finish_kernel(const double* obj_part, int nchunks,
                                                                      const double* bp, int nblk, int check,
-                                                                     double gamma, double* out6)
+                                                                     double gamma, double* out6,
+                                                                     const double* corr)
 {
     __shared__ double red[9 * kSW];
     __shared__ double v[9];
-    reduce_scalars(obj_part, nchunks, bp, nblk, v, red);
+    reduce_scalars(obj_part, nchunks, bp, nblk, v, red, check ? corr : nullptr);
     if (threadIdx.x == 0) {
         const double reg = 0.5 * gamma * v[1];
         const double g = -v[0] + reg - v[3];
@@ -301,10 +327,10 @@ __global__ __launch_bounds__(kScalarThreads) void eval_finish_kernel(const doubl
 }
 
 hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double* blockpart, int nblk,
-                              int check, double gamma, double* out6, hipStream_t s)
+                              int check, double gamma, double* out6, hipStream_t s, const double* corr_part)
 {
     hipLaunchKernelGGL(eval_finish_kernel, dim3(1), dim3(kScalarThreads), 0, s, obj_part, nchunks, blockpart,
-                       nblk, check, gamma, out6);
+                       nblk, check, gamma, out6, corr_part);
     return hipGetLastError();
 }
 
@@ -334,7 +360,7 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
         cur_ks = st->ks;
         cur_stage = st->stage;
     }
-    reduce_scalars(a.obj_part, a.nchunks, a.blockpart, a.nblk, v, red);
+    reduce_scalars(a.obj_part, a.nchunks, a.blockpart, a.nblk, v, red, a.check ? a.corr_part : nullptr);
     const SolveParams& P = a.prm;
     if (threadIdx.x == 0) {
         const int64_t k = cur_k;

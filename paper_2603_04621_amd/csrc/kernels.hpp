@@ -32,6 +32,14 @@ struct GradArgs {
     double* obj_part;        // [nchunks][3]: sum t x, sum v^2 x^2, sum c x (check)
     int32_t det, pad_det;    // deterministic mode: fixed-point integer sums
     double qs[3];            // their scales (a x, c x, v^2 x^2)
+    // columns with several entries (grad_mf_kernel): planes 1..nf-1 of the
+    // coefficients and rows (plane 0 is A, dst)
+    const void* A2[kMfPlanes - 1];
+    const int32_t* dst2[kMfPlanes - 1];
+    int32_t nf;              // entries per column (1: the one-family kernels)
+    int32_t restore;         // restoration pass of the gap (see grad_mf.hpp)
+    const double* srow;      // [J] min(1, b_j / (A x)_j), internal row order
+    double* corr_part;       // [nchunks] restoration correction of P
 };
 
 // Per-destination combination of the chunk partial sums.
@@ -55,6 +63,7 @@ struct ReduceArgs {
     double* blockpart;       // [gridDim.x][kRedStride]
     int32_t det, pad_det;    // partials and accumulators are 64-bit integers
     double iqs[3];           // their inverse scales
+    double* srow;            // check passes of multi-entry columns: out s_j, or null
 };
 
 struct AgdArgs {
@@ -71,6 +80,7 @@ struct AgdArgs {
     double* lam_eval;
     const double* D;
     double* trace;           // [max_iters][6] or null
+    const double* corr_part; // [nchunks] restoration corrections (multi-entry columns), or null
 };
 
 // dynamic LDS of a gradient launch.  Ordinary passes: lam (FP64) and the
@@ -89,7 +99,11 @@ hipError_t launch_agd(const AgdArgs& a, hipStream_t s);
 hipError_t launch_permute_in(const double* src, const int32_t* orig, int J, double* dst,
                              hipStream_t s);
 hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double* blockpart,
-                              int nblk, int check, double gamma, double* out6, hipStream_t s);
+                              int nblk, int check, double gamma, double* out6, hipStream_t s,
+                              const double* corr_part = nullptr);
+// multi-entry columns: the fused gradient pass (or, with a.restore, the
+// restoration pass); storage as launch_grad
+hipError_t launch_grad_mf(const GradArgs& a, int storage, bool has_w, hipStream_t s);
 hipError_t launch_solve_init(SolveState* st, SolveParams prm, const double* lam_in,
                              const int32_t* orig, const double* D, int J, double* lam, double* y,
                              double* yp, double* G, double* Gp, double* lam_eval, hipStream_t s);

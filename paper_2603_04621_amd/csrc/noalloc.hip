@@ -71,6 +71,8 @@ static size_t noalloc_bytes(const dl_problem* p, int check, size_t* off)
     off[3] = o; o = align256(o + (size_t)p->nblk2 * dl::kRedStride * sizeof(double));      // blockpart
     off[4] = o; o = align256(o + 8 * sizeof(double));                                      // scalars
     off[5] = o; o = align256(o + (size_t)(check ? 3 : 1) * p->nchunks * K * (p->det ? 8 : 4));  // partials
+    off[6] = o; o = align256(o + (p->nf > 1 ? J : 0) * sizeof(double));                   // row ratios
+    off[7] = o; o = align256(o + (p->nf > 1 ? (size_t)p->nchunks : 0) * sizeof(double));   // restoration
     return o;
 }
 
@@ -90,7 +92,7 @@ extern "C" dl_status dl_dual_grad_noalloc(dl_problem* p, const double* lambda_de
         return DL_ERR_INVALID_ARG;
     }
     const int check = eval_host ? 1 : 0;
-    size_t off[6];
+    size_t off[8];
     const size_t need = noalloc_bytes(p, check, off);
     if (need > kScratchBytes) {
         set_error("the evaluation needs %zu bytes of scratch; the static scratch holds %zu", need, kScratchBytes);
@@ -106,6 +108,8 @@ extern "C" dl_status dl_dual_grad_noalloc(dl_problem* p, const double* lambda_de
     double* blockpart = (double*)(base + off[3]);
     double* out6 = (double*)(base + off[4]);
     float* part = (float*)(base + off[5]);
+    double* srow = (double*)(base + off[6]);
+    double* corr = (double*)(base + off[7]);
 
     // the accumulators of rows beyond LDS must start at zero (the reduction
     // clears them after reading, but an earlier call may have stopped early)
@@ -118,15 +122,27 @@ extern "C" dl_status dl_dual_grad_noalloc(dl_problem* p, const double* lambda_de
     g.part = part;
     g.tail = tail;
     g.obj_part = obj_part;
+    g.srow = srow;
+    g.corr_part = corr;
     if ((e = dl::launch_grad(g, p->storage, check != 0, p->has_w != 0, p->has_cut != 0, s)) != hipSuccess)
         return dlh::hip_fail(e, "gradient kernel");
     dl::ReduceArgs r = dlh::reduce_args(p, check, 1, lam, nullptr, gamma, nullptr, grad_dev);
     r.part = part;
     r.tail = tail;
     r.blockpart = blockpart;
+    if (r.srow) r.srow = srow;
     if ((e = dl::launch_reduce(r, p->nblk2, s)) != hipSuccess) return dlh::hip_fail(e, "reduce kernel");
     if (eval_host) {
-        if ((e = dl::launch_eval_finish(obj_part, p->nchunks, blockpart, p->nblk2, 1, gamma, out6, s)) != hipSuccess)
+        if (p->nf > 1) {
+            // the gap's restoration over each edge's rows
+            dl::GradArgs gr = g;
+            gr.restore = 1;
+            gr.X = nullptr;
+            if ((e = dl::launch_grad(gr, p->storage, false, p->has_w != 0, p->has_cut != 0, s)) != hipSuccess)
+                return dlh::hip_fail(e, "restoration pass");
+        }
+        if ((e = dl::launch_eval_finish(obj_part, p->nchunks, blockpart, p->nblk2, 1, gamma, out6, s,
+                                        p->nf > 1 ? corr : nullptr)) != hipSuccess)
             return dlh::hip_fail(e, "evaluation kernel");
         double h[6];
         if ((e = hipMemcpyAsync(h, out6, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)

@@ -15,6 +15,11 @@ struct dl_problem {
     int storage = 1;
     int has_box = 0, has_w = 0, solve_ok = 1;
     int has_cut = 0;                   // some block is a capped simplex
+    int nf = 1;                        // entries per column (several families, dense rows)
+    void* A2[dl::kMfPlanes - 1] = {};  // planes 1..nf-1 of the coefficients
+    int32_t* dst2[dl::kMfPlanes - 1] = {};   // and their rows (internal order)
+    double* srow = nullptr;            // [J] restoration ratios (nf > 1)
+    double* corr_part = nullptr;       // [nchunks] restoration partials (nf > 1)
     int det = 0;                       // deterministic mode: fixed-point sums
     double qs[3] = {1.0, 1.0, 1.0};    // their scales (a x, c x, v^2 x^2)
     double anorm2 = 1.0;               // |A'|^2 of the iteration matrix (presets)
@@ -88,6 +93,8 @@ void destroy_idle(dl_problem* p);
 hipError_t ensure_grad_attributes(int device);
 
 dl_status check_solve_opts(const dl_solve_opts* o);
+// dl_problem_validate that also reports the most entries in one column
+dl_status validate_desc(const dl_problem_desc* d, const dl_problem_opts* o, int* col_entries);
 // solve parameters of problem p (its preset resolved with p's |A'|^2)
 dl::SolveParams make_params(const dl_solve_opts* o, const dl_problem* p);
 bool is_check_iter(const dl_solve_opts* o, int64_t k);

@@ -355,8 +355,10 @@ extern "C" dl_status dl_server_submit(dl_server* S, const dl_problem_desc* d, co
     dl_problem_opts popts;
     dl_problem_opts_init(&popts);
     if (po) popts = *po;
-    dl_status st = dl_problem_validate(d, &popts);
+    int col_entries = 1;
+    dl_status st = dlh::validate_desc(d, &popts, &col_entries);
     if (st != DL_OK) return st;
+    if (col_entries > 1) { set_error("served requests take one entry per column"); return DL_ERR_UNSUPPORTED; }
     st = dlh::check_solve_opts(so);
     if (st != DL_OK) return st;
     for (int64_t k = 0; k < d->nnz; ++k)

@@ -100,31 +100,36 @@ def test_validate_rejects_malformed_input():
     assert st == L.DL_ERR_INVALID_ARG
 
 
-def test_two_families_are_unsupported():
+def test_columns_with_several_entries():
+    """Several matching families (Definition 1) and the count row: up to four
+    entries per column are accepted in both layouts; a fifth is unsupported,
+    as is deterministic mode with several entries per column."""
+    multi = I.multi_family(I=20, J=4, families=3, count_row=True, seed=3, dmax=4)
+    assert np.all(np.diff(multi.colptr) == 4)
+    assert api.validate(multi, "csc") == L.DL_OK
+    assert api.validate(multi, "csr") == L.DL_OK
+    assert api.validate(multi, "csc", deterministic=True) == L.DL_ERR_UNSUPPORTED
+    assert "one entry per column" in L.last_error()
+    five = I.multi_family(I=20, J=4, families=4, count_row=True, seed=3, dmax=4)
+    assert api.validate(five, "csc") == L.DL_ERR_UNSUPPORTED
+    assert "at most 4" in L.last_error()
+    assert api.validate(five, "csr") == L.DL_ERR_UNSUPPORTED
+
+
+def test_csc_columns_may_repeat_a_row():
+    """A column listing one row twice is two entries whose coefficients add."""
     inst = small()
     hd = api._HostDesc(inst, "csc")
-    # column 0 gets a second entry (a second matching family)
     ptr = np.arange(inst.n + 1, dtype=np.int64)
     ptr[1:] += 1
-    idx = np.concatenate([[0], hd.idx]).astype(np.int32)
+    idx = np.concatenate([[hd.idx[0]], hd.idx]).astype(np.int32)
     val = np.concatenate([[1.0], hd.val])
     hd.desc.ptr = ptr.ctypes.data
     hd.desc.idx = idx.ctypes.data
     hd.desc.val = val.ctypes.data
     hd.desc.nnz = inst.n + 1
     o, _ = api.make_opts()
-    st = L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o))
-    assert st == L.DL_ERR_UNSUPPORTED
-    assert "family" in L.last_error()
-
-
-def test_csr_duplicate_column_is_unsupported():
-    inst = small()
-    hd = api._HostDesc(inst, "csr")
-    hd.idx[1] = hd.idx[0]
-    o, _ = api.make_opts()
-    st = L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o))
-    assert st in (L.DL_ERR_UNSUPPORTED, L.DL_ERR_INVALID_ARG)
+    assert L.lib().dl_problem_validate(ctypes.byref(hd.desc), ctypes.byref(o)) == L.DL_OK
 
 
 def test_solve_opts_defaults():

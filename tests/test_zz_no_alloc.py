@@ -84,3 +84,25 @@ def test_noalloc_rejects_problem_beyond_scratch(dev):
         assert "scratch" in L.last_error()
         # the problem still evaluates through the allocating entry point
         p.dual_grad(lam, 1e-2)
+
+
+def test_noalloc_columns_with_several_entries(dev):
+    """Two families and the count row: the allocation-free call (its
+    restoration pass takes the row ratios and partials from the static
+    scratch too) equals dl_dual_grad."""
+    from paper_2603_04621_amd.api import Problem
+    inst = I.multi_family(I=5_000, J=300, families=2, count_row=True, seed=31, box_frac=0.3)
+    lam = torch.from_numpy(np.random.default_rng(7).exponential(0.5, size=inst.m))
+    with Problem(inst, storage="f32") as p:
+        g_ref, x_ref, e_ref = p.dual_grad(lam, 1e-2, want_x=True, want_eval=True)
+        g_na, x_na, e_na = p.dual_grad(lam, 1e-2, want_x=True, want_eval=True, noalloc=True)
+    g_ref, g_na = g_ref.cpu().numpy(), g_na.cpu().numpy()
+    x_ref = x_ref.cpu().numpy()
+    cols = np.repeat(np.arange(inst.n), np.diff(inst.colptr))
+    val = inst.rounded("f32").val
+    scale = np.bincount(inst.rowidx, weights=np.abs(val * x_ref[cols]), minlength=inst.m) + \
+        np.abs(inst.b)
+    assert float(np.max(np.abs(g_na - g_ref) / np.maximum(scale, 1e-300))) <= 1e-5
+    assert np.array_equal(x_na.cpu().numpy(), x_ref)
+    assert abs(e_na["g"] - e_ref["g"]) <= 1e-6 * max(1.0, abs(e_ref["g"]))
+    assert abs(e_na["P"] - e_ref["P"]) <= 1e-6 * max(1.0, abs(e_ref["cx"]) + abs(e_ref["reg"]))
