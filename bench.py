@@ -27,6 +27,8 @@ The same JSON line carries:
                   p50/p99 latency
   heavy           the heavy-tailed mixed-projection workload (2M sources, 50k
                   destinations, ~60M nnz): kernel rate and roofline, FP32/BF16
+  multi_family    two matching families plus the count row (2M sources):
+                  kernel rate and roofline, continuation solve to gap 1e-4
   precision       errors against the FP64 oracle of every storage type on the
                   headline and the heavy-tailed workloads
   cpu_baseline    the oracle on one host core (bounded sample)
@@ -272,8 +274,45 @@ def headline(args, I, Problem):
     bytes_per = info["stream_bytes"]
     log(f"headline: {ips:.1f} iter/s, gradient {kms:.4f} ms, check {cms:.4f} ms")
 
-    # gamma continuation to gap 1e-4: the library's 5-stage solve (second of
-    # two runs: the first captures the graphs), then the stage rates
+    continuation = None
+    lam_c = lam
+    if not args.no_continuation:
+        continuation, lam_c = continuation_leg(args, prob)
+    out = {
+        "value": ips, "ms_per_step": el * 1e3 / args.steps,
+        "config": {"workload": (
+            "matching LP: I=%d sources, J=%d destinations, degree 1+Poisson(9), Zipf(1.1) "
+            "destinations, c=-LogNormal(0,1), a=LogNormal(0,0.5), simplex blocks, greedy-load "
+            "capacities (Appendix B), gamma=1e-3, gap test every 10 iterations"
+            % (args.sources, args.dests)),
+            "nnz": inst.n, "storage": args.storage, "seed": inst.seed},
+        "nnz_per_s": inst.n * ips,
+        "achieved_hbm_gbs": bytes_per / (kms * 1e-3) / 1e9,
+        "stream_gbs": bytes_per * ips / 1e9,
+        "grad_kernel_ms": kms, "check_kernel_ms": cms,
+        "roofline": {"bound": "hbm", "achieved": bytes_per / (kms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_per / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"large-greedy I={args.sources} J={args.dests} "
+                                                 f"{args.storage}"),
+                     "bytes_per_launch": bytes_per,
+                     "kernel": "grad_kernel, ordinary iterations (fused gather + projection + "
+                               "per-destination sums)"},
+        "final_g": r.g, "final_rel_gap": r.rel_gap,
+        "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks", "chunks",
+                                        "lds_rows", "lane_cap", "seg_rmax", "chunks_per_cu",
+                                        "tuned")},
+        "create_seconds": create_s,
+    }
+    if continuation is not None:
+        out["continuation"] = continuation
+    return headline_rest(args, Problem, inst, prob, out, lam_c, bytes_per)
+
+
+def continuation_leg(args, prob):
+    """The library's 5-stage continuation solve to gap 1e-4 (second of two
+    runs: the first captures the graphs), and the iteration rate of each
+    stage at the prices that stage starts from."""
     cont = continuation_settings()
     prob.solve(cont)
     sync()
@@ -303,35 +342,12 @@ def headline(args, I, Problem):
         "final_rel_gap": rc.rel_gap, "final_g": rc.g, "final_gamma": rc.gamma,
         "stages": stages}
     log(f"continuation: {continuation}")
-    out = {
-        "value": ips, "ms_per_step": el * 1e3 / args.steps,
-        "config": {"workload": (
-            "matching LP: I=%d sources, J=%d destinations, degree 1+Poisson(9), Zipf(1.1) "
-            "destinations, c=-LogNormal(0,1), a=LogNormal(0,0.5), simplex blocks, greedy-load "
-            "capacities (Appendix B), gamma=1e-3, gap test every 10 iterations"
-            % (args.sources, args.dests)),
-            "nnz": inst.n, "storage": args.storage, "seed": inst.seed},
-        "nnz_per_s": inst.n * ips,
-        "achieved_hbm_gbs": bytes_per / (kms * 1e-3) / 1e9,
-        "stream_gbs": bytes_per * ips / 1e9,
-        "grad_kernel_ms": kms, "check_kernel_ms": cms,
-        "roofline": {"bound": "hbm", "achieved": bytes_per / (kms * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": bytes_per / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"large-greedy I={args.sources} J={args.dests} "
-                                                 f"{args.storage}"),
-                     "bytes_per_launch": bytes_per,
-                     "kernel": "grad_kernel, ordinary iterations (fused gather + projection + "
-                               "per-destination sums)"},
-        "final_g": r.g, "final_rel_gap": r.rel_gap,
-        "continuation": continuation,
-        "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks", "chunks",
-                                        "lds_rows", "lane_cap", "seg_rmax", "chunks_per_cu",
-                                        "tuned")},
-        "create_seconds": create_s,
-    }
-    # evaluation of every storage type at the converged prices
-    lam_eval = lam_c
+    return continuation, lam_c
+
+
+def headline_rest(args, Problem, inst, prob, out, lam_eval, bytes_per):
+    """Every storage type evaluated at the converged prices (for the error
+    statement) with its own kernel rate, and the deterministic mode's cost."""
     gpu_evals = {}
     if not args.no_precision:
         gg, _, ee = prob.dual_grad(lam_eval, GAMMA, want_eval=True)
@@ -396,6 +412,46 @@ def heavy_leg(args, I, Problem):
     if not args.no_precision:
         out["precision"] = precision_statement(inst, lam.cpu().numpy(), GAMMA, gpu_evals,
                                                "prices after 200 iterations at gamma = 1e-3")
+    return out
+
+
+def multi_leg(args, I, Problem):
+    """Several matching families (Definition 1) with the global count row:
+    kernel rate and roofline of the multi-entry gradient kernel, and a
+    continuation solve to gap 1e-4 (natural steps from the power-iteration
+    |A'|^2)."""
+    t0 = time.perf_counter()
+    inst = I.multi_family(I=args.multi_sources, J=args.multi_dests, families=2, count_row=True,
+                          box_frac=0.2)
+    log(f"multi-family instance: {inst.n} columns, {inst.nnz} entries in "
+        f"{time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    out = {"workload": (
+        "matching LP with 2 families and the count row: I=%d sources, J=%d destinations per "
+        "family (%d rows), degree 1+Poisson(9), Zipf(1.1), a^k = LogNormal(0,0.5) per family, "
+        "greedy-load capacities per family, count cap 0.5 I, 80%% simplex / 20%% box blocks, "
+        "FP32, gamma=1e-3" % (args.multi_sources, args.multi_dests, inst.m)),
+        "columns": inst.n, "entries": inst.nnz}
+    with Problem(inst, storage="f32") as p:
+        info = p.info()
+        out["create_seconds"] = time.perf_counter() - t0
+        out["anorm2"] = info["anorm2"]
+        cont = continuation_settings(gamma_final=GAMMA, max_iters=20000)
+        sync()
+        t1 = time.perf_counter()
+        lam, r = p.solve(cont)
+        sync()
+        out["continuation"] = {"converged": bool(r.converged), "iterations": int(r.iters),
+                               "seconds": time.perf_counter() - t1, "rel_gap": r.rel_gap}
+        _, _, el = graph_rate(p, GAMMA, args.steps, args.warmup, lam0=lam)
+        kms, cms = kernel_times(p, GAMMA, max(args.steps, 100), lam0=lam)
+        sb = info["stream_bytes"]
+        out.update({"iter_per_s": args.steps / el, "grad_kernel_ms": kms, "check_kernel_ms": cms,
+                    "bytes_per_launch": sb, "achieved_gbs": sb / (kms * 1e-3) / 1e9,
+                    "frac": sb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks",
+                                                    "chunks", "lds_rows", "col_entries")}})
+    log(f"multi-family: {out}")
     return out
 
 
@@ -646,6 +702,11 @@ def main():
     ap.add_argument("--heavy-sources", type=int, default=2_000_000)
     ap.add_argument("--heavy-dests", type=int, default=50_000)
     ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tailed leg")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-family leg")
+    ap.add_argument("--no-continuation", action="store_true",
+                    help="skip the continuation solve and the per-stage rates")
+    ap.add_argument("--multi-sources", type=int, default=2_000_000)
+    ap.add_argument("--multi-dests", type=int, default=10_000)
     ap.add_argument("--no-systems", action="store_true",
                     help="skip the batched and served legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -708,6 +769,8 @@ def main():
         out["served_p99_latency_s"] = out["served"]["p99_latency_s"]
     if not args.no_heavy:
         out["heavy"] = heavy_leg(args, I, Problem)
+    if not args.no_multi:
+        out["multi_family"] = multi_leg(args, I, Problem)
     if args.ablations:
         out["ablations"] = ablations(args, I, Problem)
     if not args.no_precision and gpu_evals:

@@ -8,9 +8,12 @@
  *     g(lam) = min_{x in C} c'x + gamma/2 |D_v x|^2 + lam'(A x - b)   (Eq.(2))
  *
  * over lam >= 0 (Section 3.1), for the matching structure of Section 3.2:
- * every column of A holds at most one nonzero (one matching family,
- * A = [D_1 ... D_I] with diagonal D_i), and the columns are grouped into
- * contiguous blocks, one per source, each carrying one simple constraint:
+ * a column (one per edge) holds one nonzero per matching family, A = [D_1
+ * ... D_I] with diagonal D_i for one family and the stacked families of
+ * Definition 1 for several, plus dense rows such as the global count
+ * constraint sum x <= cap of Section 4 (at most four entries per column in
+ * all), and the columns are grouped into contiguous blocks, one per source,
+ * each carrying one simple constraint:
  * the simplex {x >= 0, sum x <= 1} (Eq.(4),(5)), a box {0 <= x <= u} or
  * both at once (dl_proj).
  * By Danskin's theorem grad g(lam) = A x*(lam) - b with
@@ -82,8 +85,11 @@ typedef struct dl_server dl_server;
  *           non-decreasing, block_off[num_blocks] = n); block_proj[num_blocks]
  *           holds dl_proj values; upper[n] bounds u (NULL = 1.0; ignored on
  *           simplex blocks).
- * Requirements: indices in range, values finite, at most one entry per column
- * (several families are DL_ERR_UNSUPPORTED), upper >= 0, m >= 1.
+ * Requirements: indices in range, values finite, at most four entries per
+ * column (more: DL_ERR_UNSUPPORTED), upper >= 0, m >= 1.  Columns with
+ * several entries (several families, dense rows) run a kernel variant of
+ * their own; dl_batch_solve, the server and deterministic mode take one
+ * entry per column (DL_ERR_UNSUPPORTED otherwise).
  * dl_solve additionally needs a >= 0 and b >= 0 (the duality-gap restoration
  * relies on them); other signs still allow dl_dual_grad. */
 typedef struct {
@@ -336,7 +342,10 @@ typedef struct {
     int32_t tuned;             /* 1 when the layout was picked by autotune        */
     double anorm2;             /* |A'|^2 of the iteration matrix (see preset): 1
                                   with row normalization and one family, else
-                                  max_j |(A D_v^{-1})_j*|^2 (rows are orthogonal)  */
+                                  max_j |(A D_v^{-1})_j*|^2 (rows are orthogonal);
+                                  with several entries per column the largest
+                                  eigenvalue of A'A'^T by power iteration,
+                                  raised by 1e-3                                 */
     int32_t deterministic;     /* 1 when created with deterministic = 1          */
     int32_t has_capped;        /* 1 when some block is DL_PROJ_CAPPED            */
     int32_t col_entries;       /* most entries in one column (1: one family)     */
