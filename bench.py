@@ -353,6 +353,9 @@ def headline_rest(args, Problem, inst, prob, out, lam_eval, bytes_per):
         gg, _, ee = prob.dual_grad(lam_eval, GAMMA, want_eval=True)
         gpu_evals[args.storage] = (ee["g"], gg.cpu().numpy())
     prob.close()
+    if not args.no_autotune_report and not args.autotune and args.storage == "f32":
+        out["autotune"] = tune_report(args, Problem, inst, None, out["grad_kernel_ms"],
+                                      out["check_kernel_ms"], out["create_seconds"])
     storages = {}
     if not args.no_precision:
         for st in ("bf16", "f64"):
@@ -377,6 +380,26 @@ def headline_rest(args, Problem, inst, prob, out, lam_eval, bytes_per):
     return out, inst, lam_eval.cpu().numpy(), gpu_evals
 
 
+def tune_report(args, Problem, inst, lam, ref_kms, ref_cms, ref_create_s):
+    """The layout autotune on this workload: its pick, the kernel times of
+    the tuned layout at the same prices and their gain over the default,
+    and what the tuning adds to create."""
+    from paper_2603_04621_amd.api import LAYOUT_KEYS
+    t0 = time.perf_counter()
+    with Problem(inst, storage="f32", autotune=True) as p:
+        create_s = time.perf_counter() - t0
+        info = p.info()
+        kms, cms = kernel_times(p, GAMMA, max(args.steps, 100), lam0=lam)
+    out = {"pick": {k: info[k] for k in LAYOUT_KEYS},
+           "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks")},
+           "grad_kernel_ms": kms, "check_kernel_ms": cms,
+           "default_grad_kernel_ms": ref_kms, "default_check_kernel_ms": ref_cms,
+           "gain": ref_kms / kms, "check_gain": ref_cms / cms,
+           "create_seconds": create_s, "default_create_seconds": ref_create_s}
+    log(f"autotune: {out}")
+    return out
+
+
 def heavy_leg(args, I, Problem):
     """The heavy-tailed workload at full size: kernel rate and roofline for
     FP32 and BF16 storage, and the error statement of every storage type."""
@@ -392,8 +415,10 @@ def heavy_leg(args, I, Problem):
     lam = None
     gpu_evals = {}
     for st in ("f32", "bf16", "f64"):
+        t0 = time.perf_counter()
         with Problem(inst, storage=st) as p:
             info = p.info()
+            create_s = time.perf_counter() - t0
             if lam is None:
                 # prices of a short solve at the final gamma
                 lam, _ = p.solve(fixed_settings(GAMMA, 200))
@@ -406,9 +431,13 @@ def heavy_leg(args, I, Problem):
                        "check_kernel_ms": cms, "bytes_per_launch": sb,
                        "achieved_gbs": sb / (kms * 1e-3) / 1e9,
                        "frac": sb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "create_seconds": create_s,
                        "layout": {k: info[k] for k in ("lane_groups", "seg_groups", "wg_blocks",
                                                        "chunks", "lds_rows")}}
             log(f"heavy {st}: {out[st]}")
+    if not args.no_autotune_report:
+        out["autotune"] = tune_report(args, Problem, inst, lam, out["f32"]["grad_kernel_ms"],
+                                      out["f32"]["check_kernel_ms"], out["f32"]["create_seconds"])
     if not args.no_precision:
         out["precision"] = precision_statement(inst, lam.cpu().numpy(), GAMMA, gpu_evals,
                                                "prices after 200 iterations at gamma = 1e-3")
@@ -727,6 +756,8 @@ def main():
     ap.add_argument("--ablation-dests", type=int, default=10_000)
     ap.add_argument("--ablation-iters", type=int, default=2000)
     ap.add_argument("--ablation-gap-iters", type=int, default=20000)
+    ap.add_argument("--no-autotune-report", action="store_true",
+                    help="skip the autotuned layouts of the headline and heavy-tailed workloads")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the work layout by timing candidates on a sample at create")
     ap.add_argument("--cache", default=None,

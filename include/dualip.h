@@ -115,12 +115,18 @@ typedef struct {
  *   v              [n] host array of positive scales when primal_scale = 2.
  *   autotune       0 (default): the work layout follows the kernel variant's
  *                  register budget (largest one-lane blocks, rows per lane,
- *                  one workgroup per compute unit).  1: before building the
- *                  problem, time the gradient kernel on a sample of its blocks
- *                  (every k-th block, about 16M nonzeros, same destinations)
- *                  for each candidate layout (smaller one-lane blocks, fewer
- *                  rows per lane, two workgroups per compute unit) at lambda =
- *                  0 and keep the fastest; costs a few sample builds at create.
+ *                  workgroup blocks only beyond 64-lane segments, one
+ *                  workgroup per compute unit).  1: before building the
+ *                  problem, build a sample of it (every k-th block, about 16M
+ *                  nonzeros, all destinations, capacities scaled by the
+ *                  sampled fraction), run 200 iterations of the solver on it
+ *                  at gamma = 1e-3 (natural steps) for representative prices,
+ *                  then time the gradient kernel at those prices while
+ *                  changing one layout parameter at a time (largest one-lane
+ *                  block, rows per lane, smallest workgroup block,
+ *                  workgroups per compute unit), keeping a change only when
+ *                  it is at least 1% faster; costs about a dozen sample
+ *                  builds at create.  dl_problem_info reports the pick.
  *   deterministic  0 (default): the per-destination sums of A x (and of the
  *                  gap terms) are f32 partials added by LDS atomics in
  *                  whatever order the waves reach them, so two evaluations
@@ -132,6 +138,17 @@ typedef struct {
  *                  order-independent: dl_dual_grad and dl_solve return the same
  *                  bits on every run.  Costs LDS (16 instead of 12 bytes per
  *                  row kept in LDS) and integer conversions per term.
+ *   lane_cap, seg_rmax, wg_min, chunks_per_cu
+ *                  the work layout by hand (0 = the default of each; the
+ *                  starting point of autotune when it is on): largest degree
+ *                  of a block on one lane, largest rows per lane of a block
+ *                  on 4, 16 or 64 lanes, smallest degree of a block on a
+ *                  whole workgroup (beyond the one-lane ones), workgroups of
+ *                  the gradient kernel per compute unit.  The first two are
+ *                  clamped to the kernel variant's register budget; a wg_min
+ *                  above 64 seg_rmax changes nothing.  Values below 0, or
+ *                  chunks_per_cu above 8, are DL_ERR_INVALID_ARG.  Only the
+ *                  speed changes: results agree to rounding with the default.
  * The regularizer is gamma/2 sum_e v_e^2 x_e^2 (view (i) of primal scaling). */
 typedef struct {
     dl_storage storage;
@@ -140,10 +157,11 @@ typedef struct {
     const double* v;
     int32_t autotune;
     int32_t deterministic;
+    int32_t lane_cap, seg_rmax, wg_min, chunks_per_cu;
 } dl_problem_opts;
 
 /* Fills opts with the defaults (DL_F32, row_normalize = 1, primal_scale = 0,
- * autotune = 0, deterministic = 0). */
+ * autotune = 0, deterministic = 0, layout fields 0). */
 void dl_problem_opts_init(dl_problem_opts* opts);
 
 /* Host-only validation of desc/opts with the rules above; no device is
@@ -349,7 +367,9 @@ typedef struct {
     int32_t deterministic;     /* 1 when created with deterministic = 1          */
     int32_t has_capped;        /* 1 when some block is DL_PROJ_CAPPED            */
     int32_t col_entries;       /* most entries in one column (1: one family)     */
-    int32_t reserved;
+    int32_t wg_min;            /* blocks of at least this many edges (beyond the
+                                  one-lane ones) run on a whole workgroup; 0:
+                                  only blocks longer than 64 seg_rmax do        */
 } dl_problem_info;
 dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* info);
 

@@ -41,7 +41,9 @@ class ProblemDesc(ctypes.Structure):
 
 class ProblemOpts(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int), ("row_normalize", c_i32), ("primal_scale", c_i32),
-                ("v", c_ptr), ("autotune", c_i32), ("deterministic", c_i32)]
+                ("v", c_ptr), ("autotune", c_i32), ("deterministic", c_i32),
+                ("lane_cap", c_i32), ("seg_rmax", c_i32), ("wg_min", c_i32),
+                ("chunks_per_cu", c_i32)]
 
 
 class Eval(ctypes.Structure):
@@ -71,7 +73,7 @@ class ProblemInfo(ctypes.Structure):
                                      "device_bytes")] + [(k, c_i32) for k in (
                     "storage", "has_box", "lane_cap", "seg_rmax", "chunks_per_cu", "tuned")] + [
                     ("anorm2", c_dbl), ("deterministic", c_i32), ("has_capped", c_i32),
-                    ("col_entries", c_i32), ("reserved", c_i32)]
+                    ("col_entries", c_i32), ("wg_min", c_i32)]
 
 
 # every symbol include/dualip.h declares

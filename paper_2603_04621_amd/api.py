@@ -61,8 +61,12 @@ class _HostDesc:
                                   _np_ptr(self.upper))
 
 
+LAYOUT_KEYS = ("lane_cap", "seg_rmax", "wg_min", "chunks_per_cu")
+
+
 def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: int = 0, v=None,
-              autotune: bool = False, deterministic: bool = False):
+              autotune: bool = False, deterministic: bool = False, work_layout=None):
+    """dl_problem_opts; work_layout: dict with any of LAYOUT_KEYS (0 = default)."""
     o = L.ProblemOpts()
     L.lib().dl_problem_opts_init(ctypes.byref(o))
     o.storage = L.STORAGE[storage]
@@ -70,6 +74,10 @@ def make_opts(storage: str = "f32", row_normalize: bool = True, primal_scale: in
     o.primal_scale = int(primal_scale)
     o.autotune = 1 if autotune else 0
     o.deterministic = 1 if deterministic else 0
+    for k, val in (work_layout or {}).items():
+        if k not in LAYOUT_KEYS:
+            raise KeyError(k)
+        setattr(o, k, int(val))
     keep = None
     if v is not None:
         keep = np.ascontiguousarray(v, dtype=np.float64)
@@ -159,12 +167,13 @@ class Problem:
 
     def __init__(self, inst, storage: str = "f32", row_normalize: bool = True,
                  primal_scale: int = 0, v=None, layout: str = "csc", stream=None,
-                 autotune: bool = False, deterministic: bool = False):
+                 autotune: bool = False, deterministic: bool = False, work_layout=None):
         import torch
         self.m, self.n = int(inst.m), int(inst.n)
         self.device = torch.device("cuda", torch.cuda.current_device())
         hd = _HostDesc(inst, layout)
-        o, _keep = make_opts(storage, row_normalize, primal_scale, v, autotune, deterministic)
+        o, _keep = make_opts(storage, row_normalize, primal_scale, v, autotune, deterministic,
+                             work_layout)
         h = ctypes.c_void_p()
         L.check(L.lib().dl_problem_create(ctypes.byref(hd.desc), ctypes.byref(o),
                                           _stream(stream), ctypes.byref(h)), "dl_problem_create")

@@ -5,6 +5,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -79,6 +80,7 @@ extern "C" void dl_problem_opts_init(dl_problem_opts* o)
     o->v = nullptr;
     o->autotune = 0;
     o->deterministic = 0;
+    o->lane_cap = o->seg_rmax = o->wg_min = o->chunks_per_cu = 0;
 }
 
 extern "C" void dl_solve_opts_init(dl_solve_opts* o)
@@ -196,6 +198,9 @@ static dl_status validate_impl(const dl_problem_desc* d, const dl_problem_opts* 
         if (o->primal_scale < 0 || o->primal_scale > 2) { set_error("primal_scale must be 0, 1 or 2"); return DL_ERR_INVALID_ARG; }
         if (o->deterministic != 0 && o->deterministic != 1) { set_error("deterministic must be 0 or 1"); return DL_ERR_INVALID_ARG; }
         if (o->deterministic && maxk > 1) { set_error("deterministic mode supports one entry per column only"); return DL_ERR_UNSUPPORTED; }
+        if (o->lane_cap < 0 || o->seg_rmax < 0 || o->wg_min < 0 || o->chunks_per_cu < 0 || o->chunks_per_cu > 8) {
+            set_error("layout fields must be >= 0 (chunks_per_cu <= 8)"); return DL_ERR_INVALID_ARG;
+        }
         if (o->primal_scale == 2) {
             if (!o->v) { set_error("primal_scale = 2 needs v"); return DL_ERR_INVALID_ARG; }
             for (int64_t e = 0; e < d->n; ++e)
@@ -257,12 +262,13 @@ struct HostLayout {
     int64_t n_lane = 0, n_seg = 0, n_wg = 0;   // one-lane groups, multi-lane groups, WG blocks
 };
 
-// Lanes per block (log2) of a block of d edges: 0 up to cap, else the
-// smallest S in {4, 16, 64} with ceil(d / S) <= rmax rows per lane; -1 for
-// WG blocks.
-static int block_lg(int64_t d, int cap, int rmax)
+// Lanes per block (log2) of a block of d edges: 0 up to cap, else -1 (a WG
+// block) from wgmin edges on (wgmin > 0), else the smallest S in {4, 16, 64}
+// with ceil(d / S) <= rmax rows per lane; -1 for longer blocks.
+static int block_lg(int64_t d, int cap, int rmax, int wgmin)
 {
     if (d <= cap) return 0;
+    if (wgmin > 0 && d >= wgmin) return -1;
     for (int lg = 2; lg <= 6; lg += 2)
         if ((d + (1 << lg) - 1) >> lg <= rmax) return lg;
     return -1;
@@ -275,7 +281,7 @@ static int block_lg(int64_t d, int cap, int rmax)
 // and of very different sizes, go in decreasing size with the direction of
 // the deal reversed every round) and lays the stream out chunk by chunk, so
 // each workgroup reads one contiguous region per kind.
-static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, HostLayout& L)
+static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, int wgmin, HostLayout& L)
 {
     const int64_t I = d->num_blocks;
     const int64_t dmax_lane = std::max<int64_t>(cap, 64 * (int64_t)rmax);
@@ -291,8 +297,8 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
         const int pr = d->block_proj[i];
         if (deg == 0) continue;
         // capped-simplex blocks: smaller one-lane and per-lane classes
-        const int lg = pr == DL_PROJ_CAPPED ? block_lg(deg, std::min(cap, kCutLaneCap), std::min(rmax, kCutRmax))
-                                            : block_lg(deg, cap, rmax);
+        const int lg = pr == DL_PROJ_CAPPED ? block_lg(deg, std::min(cap, kCutLaneCap), std::min(rmax, kCutRmax), wgmin)
+                                            : block_lg(deg, cap, rmax, wgmin);
         if (lg >= 0) bucket(lg, pr, deg).push_back(i);
         else wgb.push_back({(int64_t)pr, i});
     }
@@ -438,7 +444,9 @@ static void free_problem(dl_problem* p)
 // Work layout of a problem: largest one-lane degree and rows per lane (each
 // clamped to the kernel variant's register budget) and workgroups per CU.
 struct LayoutChoice {
-    int lane_cap = 1 << 30, seg_rmax = 1 << 30, chunk_mult = 1, tuned = 0;
+    // wg_min: blocks of at least this many edges (beyond the one-lane ones)
+    // are WG items; 0: only those too long for 64-lane segments
+    int lane_cap = 1 << 30, seg_rmax = 1 << 30, chunk_mult = 1, wg_min = 0, tuned = 0;
 };
 
 static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& opts, hipStream_t s,
@@ -632,7 +640,9 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     }
     p->chunk_mult = lc.chunk_mult;
     p->tuned = lc.tuned;
-    build_items(d, nch, p->lane_cap, p->seg_rmax, L);
+    // a threshold beyond what 64-lane segments hold changes nothing
+    p->wg_min = lc.wg_min > 0 && lc.wg_min <= 64 * p->seg_rmax ? std::max(lc.wg_min, p->lane_cap + 1) : 0;
+    build_items(d, nch, p->lane_cap, p->seg_rmax, p->wg_min, L);
     p->nchunks = nch;
     p->nitems = (int)L.items.size();
     p->n_lane = L.n_lane;
@@ -788,10 +798,19 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
 }
 
 // Autotune: every k-th block of the problem (about kTuneNnz nonzeros, all m
-// destinations, same projection types and scales) is built with each
-// candidate layout and the fused gradient timed at lambda = 0, gamma = 1e-3
-// (median of 5 launches after 2 warm-up launches); the fastest wins.
+// destinations, same projection types and scales, capacities scaled by the
+// sampled fraction of nonzeros so that they bind as often as in the whole
+// problem) is solved for kTunePrices iterations at gamma = kTuneGamma with
+// natural steps; the gradient kernel is then timed at those prices for each
+// layout on a coordinate search (one parameter at a time, the others at the
+// best so far; a change is kept when it is at least kTuneGain faster).  The
+// kernel's cost depends on the prices through the projections' active sets,
+// so prices of zero (every block unconstrained by capacity) would time a
+// different mix of threshold loops than the solver runs.
 constexpr int64_t kTuneNnz = (int64_t)16 << 20;
+constexpr int kTunePrices = 200;
+constexpr double kTuneGamma = 1e-3;
+constexpr double kTuneGain = 0.01;
 
 static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& opts, hipStream_t s,
                              LayoutChoice* out)
@@ -825,6 +844,9 @@ static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& op
         off.push_back((int64_t)idx.size());
         proj.push_back(d->block_proj[i]);
     }
+    const double frac = n > 0 ? (double)idx.size() / (double)n : 1.0;
+    std::vector<double> bs((size_t)d->m);
+    for (int64_t j = 0; j < d->m; ++j) bs[j] = d->b[j] * frac;
     dl_problem_desc sd = *d;
     sd.n = sd.nnz = (int64_t)idx.size();
     sd.layout = DL_CSC;
@@ -832,6 +854,7 @@ static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& op
     sd.idx = idx.data();
     sd.val = val.data();
     sd.c = c.data();
+    sd.b = bs.data();
     sd.num_blocks = (int64_t)proj.size();
     sd.block_off = off.data();
     sd.block_proj = proj.data();
@@ -839,57 +862,99 @@ static dl_status tune_layout(const dl_problem_desc* d, const dl_problem_opts& op
     dl_problem_opts so = opts;
     so.autotune = 0;
     so.v = opts.primal_scale == 2 ? v.data() : nullptr;
+    int sample_solve_ok = 1, ce = 1;
+    dl_status st = validate_impl(&sd, &so, &sample_solve_ok, &ce);
+    if (st != DL_OK) return st;
 
     double* lam = nullptr;
     HIP_TRY(hipMalloc(&lam, (size_t)d->m * sizeof(double)), "tuning buffer");
-    dl_status st = DL_OK;
     {
         const hipError_t e = hipMemsetAsync(lam, 0, (size_t)d->m * sizeof(double), s);
         if (e != hipSuccess) st = hip_fail(e, "tuning buffer");
     }
-    // candidates: the variant's budget, smaller one-lane blocks, fewer rows
-    // per lane, two workgroups per CU
-    std::vector<LayoutChoice> cands;
-    for (int lcap : {1 << 30, 16})
-        for (int rmax : {1 << 30, 8})
-            for (int mult : {1, 2}) {
-                LayoutChoice c;
-                c.lane_cap = lcap;
-                c.seg_rmax = rmax;
-                c.chunk_mult = mult;
-                c.tuned = 1;
-                cands.push_back(c);
-            }
-    double best = INFINITY;
-    LayoutChoice pick = cands[0];
-    std::vector<std::pair<int, int>> seen;
-    for (size_t q = 0; q < cands.size() && st == DL_OK; ++q) {
+
+    // timed layouts by their effective (lane_cap, seg_rmax, wg_min, chunk_mult)
+    std::vector<std::pair<std::array<int, 4>, double>> timed;
+    bool prices = false;
+    auto time_layout = [&](const LayoutChoice& lc, double* ms_out) -> dl_status {
         dl_problem* sp = nullptr;
-        st = create_with(&sd, so, 1, cands[q], s, &sp);
-        if (st != DL_OK) break;
-        // layouts that clamp to one already timed are skipped
-        const std::pair<int, int> key(sp->lane_cap * 1000 + sp->seg_rmax, sp->chunk_mult);
-        if (std::find(seen.begin(), seen.end(), key) == seen.end()) {
-            seen.push_back(key);
-            double ms = 0.0;
-            std::vector<double> t;
-            st = dl_time_grad_kernel(sp, lam, 1e-3, 2, 0, &ms, s);
-            for (int r = 0; r < 5 && st == DL_OK; ++r) {
-                st = dl_time_grad_kernel(sp, lam, 1e-3, 1, 0, &ms, s);
-                t.push_back(ms);
-            }
-            if (st == DL_OK) {
-                std::sort(t.begin(), t.end());
-                if (t[t.size() / 2] < best) {
-                    best = t[t.size() / 2];
-                    pick = cands[q];
+        dl_status r = create_with(&sd, so, sample_solve_ok, lc, s, &sp);
+        if (r != DL_OK) return r;
+        if (!prices) {
+            // representative prices from the first layout built (a solve's
+            // iterates do not depend on the layout beyond rounding order)
+            prices = true;
+            if (sample_solve_ok) {
+                dl_solve_opts o;
+                dl_solve_opts_init(&o);
+                o.gamma0 = o.gamma_final = kTuneGamma;
+                o.max_iters = kTunePrices;
+                o.tol_rel_gap = -1.0;
+                o.preset = DL_PRESET_NATURAL;
+                dl_solve_result res;
+                const dl_status rs = dl_solve(sp, &o, lam, &res, s);
+                if (rs != DL_OK && rs != DL_ERR_NOT_CONVERGED) {
+                    // no usable prices (a non-finite objective): time at zero
+                    const hipError_t e = hipMemsetAsync(lam, 0, (size_t)d->m * sizeof(double), s);
+                    if (e != hipSuccess) r = hip_fail(e, "tuning buffer");
                 }
             }
         }
+        const std::array<int, 4> key{sp->lane_cap, sp->seg_rmax, sp->wg_min, sp->chunk_mult};
+        for (auto& kv : timed)
+            if (kv.first == key) {
+                *ms_out = kv.second;
+                dl_problem_destroy(sp);
+                return r;
+            }
+        std::vector<double> t;
+        double ms = 0.0;
+        if (r == DL_OK) r = dl_time_grad_kernel(sp, lam, kTuneGamma, 4, 0, &ms, s);
+        for (int q = 0; q < 5 && r == DL_OK; ++q) {
+            r = dl_time_grad_kernel(sp, lam, kTuneGamma, 4, 0, &ms, s);
+            t.push_back(ms);
+        }
         dl_problem_destroy(sp);
+        if (r != DL_OK) return r;
+        std::sort(t.begin(), t.end());
+        *ms_out = t[t.size() / 2];
+        timed.push_back({key, *ms_out});
+        return DL_OK;
+    };
+
+    LayoutChoice best = *out;   // the caller's layout (defaults where unset)
+    best.tuned = 1;
+    double best_ms = INFINITY;
+    if (st == DL_OK) st = time_layout(best, &best_ms);
+    // coordinate search: largest one-lane block, rows per lane, smallest
+    // workgroup block, workgroups per CU
+    const int lcaps[] = {24, 16, 8};
+    const int rmaxs[] = {12, 8, 4};
+    const int wgmins[] = {2048, 1024, 512, 256};
+    const int mults[] = {2};
+    for (int axis = 0; axis < 4 && st == DL_OK; ++axis) {
+        const int* vals = axis == 0 ? lcaps : axis == 1 ? rmaxs : axis == 2 ? wgmins : mults;
+        const int nv = axis == 0 ? 3 : axis == 1 ? 3 : axis == 2 ? 4 : 1;
+        LayoutChoice axis_best = best;
+        double axis_ms = best_ms;
+        for (int q = 0; q < nv && st == DL_OK; ++q) {
+            LayoutChoice cand = best;
+            int& slot = axis == 0 ? cand.lane_cap : axis == 1 ? cand.seg_rmax : axis == 2 ? cand.wg_min : cand.chunk_mult;
+            slot = vals[q];
+            double ms = 0.0;
+            st = time_layout(cand, &ms);
+            if (st == DL_OK && ms < axis_ms) {
+                axis_ms = ms;
+                axis_best = cand;
+            }
+        }
+        if (axis_ms < best_ms * (1.0 - kTuneGain)) {
+            best = axis_best;
+            best_ms = axis_ms;
+        }
     }
     (void)hipFree(lam);
-    if (st == DL_OK) *out = pick;
+    if (st == DL_OK) *out = best;
     return st;
 }
 
@@ -907,6 +972,10 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, const dl_proble
     if (st != DL_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     LayoutChoice lc;
+    if (opts.lane_cap > 0) lc.lane_cap = opts.lane_cap;
+    if (opts.seg_rmax > 0) lc.seg_rmax = opts.seg_rmax;
+    if (opts.wg_min > 0) lc.wg_min = opts.wg_min;
+    if (opts.chunks_per_cu > 0) lc.chunk_mult = opts.chunks_per_cu;
     // (multi-entry columns keep the default layout: the tuner samples one
     // entry per column)
     if (opts.autotune && col_entries <= 1) {
@@ -965,7 +1034,7 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* p, dl_problem_info* i
     info->deterministic = p->det;
     info->has_capped = p->has_cut;
     info->col_entries = p->nf;
-    info->reserved = 0;
+    info->wg_min = p->wg_min;
     info->lane_cap = p->lane_cap;
     info->seg_rmax = p->seg_rmax;
     info->chunks_per_cu = p->chunk_mult;

@@ -27,7 +27,7 @@ struct dl_problem {
     int Kc = 0;                        // rows of the check-pass c x, v^2 x^2 sums in LDS
     int nchunks = 0, nitems = 0, nblk2 = 0;
     int64_t n_lane = 0, n_seg = 0, n_wg = 0;
-    int lane_cap = 0, seg_rmax = 0, chunk_mult = 1, tuned = 0;   // work layout
+    int lane_cap = 0, seg_rmax = 0, chunk_mult = 1, wg_min = 0, tuned = 0;   // work layout
     int64_t stream_bytes = 0;
     size_t device_bytes = 0;
     // edge stream

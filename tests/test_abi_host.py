@@ -146,6 +146,7 @@ def test_problem_opts_defaults_and_autotune_flag():
     o, _ = api.make_opts()
     assert o.storage == L.STORAGE["f32"] and o.row_normalize == 1 and o.primal_scale == 0
     assert o.autotune == 0 and o.deterministic == 0
+    assert (o.lane_cap, o.seg_rmax, o.wg_min, o.chunks_per_cu) == (0, 0, 0, 0)
     inst = I.tiny()
     hd = api._HostDesc(inst, "csc")
     o.autotune = 2
@@ -182,3 +183,16 @@ def test_solve_presets_host_side():
     o.preset = L.DL_PRESET_PAPER
     assert L.lib().dl_solve_opts_apply_preset(ctypes.byref(o), 0.0) == L.DL_ERR_INVALID_ARG
     assert L.lib().dl_solve_opts_apply_preset(ctypes.byref(o), float("nan")) == L.DL_ERR_INVALID_ARG
+
+
+def test_work_layout_fields_are_validated():
+    """Layout fields by hand: 0 and positive values pass, negative ones and
+    more than 8 workgroups per compute unit are rejected on the host."""
+    inst = small()
+    assert api.validate(inst, work_layout={"lane_cap": 8, "seg_rmax": 2, "wg_min": 100,
+                                            "chunks_per_cu": 8}) == L.DL_OK
+    for bad in ({"lane_cap": -1}, {"seg_rmax": -2}, {"wg_min": -5}, {"chunks_per_cu": 9}):
+        assert api.validate(inst, work_layout=bad) == L.DL_ERR_INVALID_ARG
+        assert "layout" in L.last_error()
+    with pytest.raises(KeyError):
+        api.make_opts(work_layout={"lanes": 3})

@@ -41,7 +41,7 @@ def gpu_problem(inst, storage="f32", **kw):
 
 
 def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc", v=None,
-            primal_scale=0, autotune=False, deterministic=False):
+            primal_scale=0, autotune=False, deterministic=False, work_layout=None):
     """Runs one evaluation on both sides; returns the measured errors."""
     ref_inst = inst.rounded(storage)
     vv = None
@@ -56,7 +56,7 @@ def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc
         v_dev = 1.0 / np.sqrt((1.0 / vv ** 2).astype(np.float32).astype(np.float64))
     ev = O.dual_eval(ref_inst, lam, gamma, v=v_dev)
     with gpu_problem(inst, storage, layout=layout, primal_scale=primal_scale, v=v,
-                     autotune=autotune, deterministic=deterministic) as p:
+                     autotune=autotune, deterministic=deterministic, work_layout=work_layout) as p:
         grad, x, e = p.dual_grad(torch.from_numpy(lam), gamma, want_x=True, want_eval=True)
         grad = grad.cpu().numpy()
         x = x.cpu().numpy()
@@ -211,14 +211,41 @@ def test_grad_rows_beyond_lds(O, dev):
 
 
 def test_autotuned_layout_matches_oracle(O, dev):
-    """A problem built with autotune (candidate layouts timed on a sample of
-    its blocks) reports the chosen layout and gives the oracle's gradient."""
+    """A problem built with autotune (layouts timed on a sample of its blocks
+    at the prices of a short solve) reports the chosen layout and gives the
+    oracle's gradient."""
     inst = I.heavy(I=12_000, J=3_000, dmax=2048, capacity="greedy")
     with gpu_problem(inst, "f32", autotune=True) as p:
         info = p.info()
     assert info["tuned"] == 1 and info["chunks_per_cu"] in (1, 2)
-    assert info["lane_cap"] in (16, 32) and info["seg_rmax"] in (8, 16)
+    assert info["lane_cap"] in (8, 16, 24, 32) and info["seg_rmax"] in (4, 8, 12, 16)
+    assert info["wg_min"] in (0, 256, 512, 1024)
     compare(O, inst, "f32", lam_for(inst, 14, 2.0), 1e-2, autotune=True)
+
+
+@pytest.mark.parametrize("wl", [
+    {"lane_cap": 8, "seg_rmax": 4, "wg_min": 256, "chunks_per_cu": 2},
+    {"wg_min": 33},
+    {"lane_cap": 1, "seg_rmax": 1, "chunks_per_cu": 3},
+    {"lane_cap": 24, "seg_rmax": 12, "wg_min": 512},
+])
+def test_work_layouts_by_hand(O, dev, wl):
+    """Layouts set by hand (the tuner's search space and its corners: every
+    block of more than one edge on segments, blocks from 33 edges on whole
+    workgroups) give the oracle's gradient on simplex, box and capped blocks
+    of degrees 1..2048, in both storages; the info reports the layout."""
+    inst = I.heavy(I=6_000, J=2_000, dmax=2048, capacity="greedy", box_frac=0.3, capped_frac=0.2,
+                   seed=31)
+    with gpu_problem(inst, "f32", work_layout=wl) as p:
+        info = p.info()
+    for k, val in wl.items():
+        if k == "wg_min":
+            assert info[k] == max(val, info["lane_cap"] + 1)
+        else:
+            assert info[k] == val, (k, info[k])
+    assert info["wg_blocks"] > 0 and info["tuned"] == 0
+    compare(O, inst, "f32", lam_for(inst, 15, 1.0), 1e-2, work_layout=wl)
+    compare(O, inst, "f64", lam_for(inst, 16, 1.0), 1e-3, grad_tol=1e-5, work_layout=wl)
 
 
 def test_grad_csr_equals_csc(O, dev):
