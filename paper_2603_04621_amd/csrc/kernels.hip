@@ -239,9 +239,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs r) { red
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel_batch(const ReduceArgs* __restrict__ tab,
                                                            const int2* __restrict__ rt)
 {
+    // the arguments stay in memory (a copy would be indexed by the plane and
+    // go to scratch)
     const int2 e = rt[blockIdx.x];
-    const ReduceArgs r = tab[e.x];
-    reduce_body(r, e.y);
+    reduce_body(tab[e.x], e.y);
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, int nblk, hipStream_t s)
