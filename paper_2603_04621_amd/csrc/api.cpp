@@ -263,15 +263,28 @@ struct HostLayout {
 };
 
 // Lanes per block (log2) of a block of d edges: 0 up to cap, else -1 (a WG
-// block) from wgmin edges on (wgmin > 0), else the smallest S in {4, 16, 64}
-// with ceil(d / S) <= rmax rows per lane; -1 for longer blocks.
-static int block_lg(int64_t d, int cap, int rmax, int wgmin)
+// block) from wgmin edges on (wgmin > 0); else, among S = 2^lg (lg = 1..6,
+// or 2, 4, 6 when even) with R = ceil(d / S) <= rmax rows per lane, the S
+// whose register rows pad the block least: the kernel holds R rows in a
+// class of 8 rows (R <= 8) or of pmax rows, so a group costs S times the
+// class in row slots (the smaller S on ties: fewer reduction steps); -1 for
+// longer blocks.
+static int block_lg(int64_t d, int cap, int rmax, int pmax, bool even, int wgmin)
 {
     if (d <= cap) return 0;
     if (wgmin > 0 && d >= wgmin) return -1;
-    for (int lg = 2; lg <= 6; lg += 2)
-        if ((d + (1 << lg) - 1) >> lg <= rmax) return lg;
-    return -1;
+    int best = -1;
+    int64_t best_slots = 0;
+    for (int lg = even ? 2 : 1; lg <= 6; lg += even ? 2 : 1) {
+        const int64_t R = (d + (1 << lg) - 1) >> lg;
+        if (R > rmax) continue;
+        const int64_t slots = ((int64_t)1 << lg) * (R <= 8 ? 8 : pmax);
+        if (best < 0 || slots < best_slots) {
+            best = lg;
+            best_slots = slots;
+        }
+    }
+    return best;
 }
 
 // Groups blocks by (lanes per block, projection, degree), deals the work
@@ -281,15 +294,16 @@ static int block_lg(int64_t d, int cap, int rmax, int wgmin)
 // and of very different sizes, go in decreasing size with the direction of
 // the deal reversed every round) and lays the stream out chunk by chunk, so
 // each workgroup reads one contiguous region per kind.
-static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, int wgmin, HostLayout& L)
+static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, int pmax, bool even, int wgmin,
+                        HostLayout& L)
 {
     const int64_t I = d->num_blocks;
     const int64_t dmax_lane = std::max<int64_t>(cap, 64 * (int64_t)rmax);
-    // buckets: [lg / 2][proj][degree] for LANE items, then WG blocks by proj
+    // buckets: [lg][proj][degree] for LANE items, then WG blocks by proj
     constexpr int NPJ = 3;   // projection types (dl_proj)
-    std::vector<std::vector<int64_t>> lane((size_t)4 * NPJ * (dmax_lane + 1));
+    std::vector<std::vector<int64_t>> lane((size_t)7 * NPJ * (dmax_lane + 1));
     auto bucket = [&](int lg, int pr, int64_t deg) -> std::vector<int64_t>& {
-        return lane[((size_t)(lg / 2) * NPJ + pr) * (dmax_lane + 1) + deg];
+        return lane[((size_t)lg * NPJ + pr) * (dmax_lane + 1) + deg];
     };
     std::vector<std::pair<int64_t, int64_t>> wgb;   // (proj, block)
     for (int64_t i = 0; i < I; ++i) {
@@ -297,8 +311,10 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
         const int pr = d->block_proj[i];
         if (deg == 0) continue;
         // capped-simplex blocks: smaller one-lane and per-lane classes
-        const int lg = pr == DL_PROJ_CAPPED ? block_lg(deg, std::min(cap, kCutLaneCap), std::min(rmax, kCutRmax), wgmin)
-                                            : block_lg(deg, cap, rmax, wgmin);
+        const int lg = pr == DL_PROJ_CAPPED
+                           ? block_lg(deg, std::min(cap, kCutLaneCap), std::min(rmax, kCutRmax),
+                                      std::min(pmax, kCutRmax), even, wgmin)
+                           : block_lg(deg, cap, rmax, pmax, even, wgmin);
         if (lg >= 0) bucket(lg, pr, deg).push_back(i);
         else wgb.push_back({(int64_t)pr, i});
     }
@@ -317,7 +333,7 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
     };
     std::vector<Proto> kinds[2];
     std::vector<int64_t> gb;
-    for (int lg = 0; lg <= 6; lg += 2)
+    for (int lg = 0; lg <= 6; ++lg)
         for (int pr = 0; pr < NPJ; ++pr)
             for (int64_t deg = 1; deg <= dmax_lane; ++deg) {
                 const auto& v = bucket(lg, pr, deg);
@@ -346,7 +362,7 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
     // deal: chunk c takes items c, c + nchunks, ... of each kind (WG items:
     // item r nchunks + c in even rounds r, r nchunks + nchunks - 1 - c in odd
     // ones); stream positions follow the final item order
-    L.chunks.assign((size_t)nchunks, Chunk{0, 0, 0, 0});
+    L.chunks.assign((size_t)nchunks, Chunk{});
     std::vector<int64_t> g0s;
     int64_t pos = 0;
     for (int k = 0; k < 2; ++k) {
@@ -366,6 +382,28 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
             }
             r[1] = (int32_t)L.items.size();
         }
+    }
+    // waves' shares of each chunk's lane items: contiguous, split at equal
+    // cost (rows of the group's register class, plus a fixed part)
+    auto item_cost = [&](const Item& it) -> int64_t {
+        int64_t rows;
+        if (it.lg == 0) rows = it.d <= 4 ? 4 : it.d <= 8 ? 8 : it.d <= 12 ? 12 : it.d <= 16 ? 16 : it.d <= 24 ? 24 : 32;
+        else rows = (((int64_t)it.d + (1 << it.lg) - 1) >> it.lg) <= 8 ? 8 : pmax;
+        return rows + 4;
+    };
+    for (int c = 0; c < nchunks; ++c) {
+        Chunk& ch = L.chunks[c];
+        int64_t tot = 0;
+        for (int32_t q = ch.a0; q < ch.a1; ++q) tot += item_cost(L.items[q]);
+        int64_t acc = 0;
+        int wv = 1;
+        ch.w[0] = ch.a0;
+        for (int32_t q = ch.a0; q < ch.a1 && wv < kWaves; ++q) {
+            acc += item_cost(L.items[q]);
+            while (wv < kWaves && acc * kWaves >= tot * wv) ch.w[wv++] = q + 1;
+        }
+        while (wv < kWaves) ch.w[wv++] = ch.a1;
+        ch.w[kWaves] = ch.a1;
     }
 
     // stream position -> original column: edge e = k S + s of block b of a
@@ -642,7 +680,11 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     p->tuned = lc.tuned;
     // a threshold beyond what 64-lane segments hold changes nothing
     p->wg_min = lc.wg_min > 0 && lc.wg_min <= 64 * p->seg_rmax ? std::max(lc.wg_min, p->lane_cap + 1) : 0;
-    build_items(d, nch, p->lane_cap, p->seg_rmax, p->wg_min, L);
+    // the kernel variant's largest row class; segments of 4, 16 or 64 lanes
+    // only for the multi-entry kernel and for the kernels of problems with
+    // capped blocks or in deterministic mode
+    const int pmax = nf > 1 ? kMfRmax : seg_rmax(f64, p->has_w != 0, tail);
+    build_items(d, nch, p->lane_cap, p->seg_rmax, pmax, nf > 1 || p->has_cut || p->det, p->wg_min, L);
     p->nchunks = nch;
     p->nitems = (int)L.items.size();
     p->n_lane = L.n_lane;

@@ -81,6 +81,10 @@ static_assert(sizeof(Item) == 16, "Item layout");
 
 struct Chunk {               // lane items [a0, a1), workgroup blocks [b0, b1)
     int32_t a0, a1, b0, b1;
+    // lane items of wave q of the one-entry kernels: [w[q], w[q + 1]), a
+    // contiguous share of [a0, a1) (items of one class stay together, so a
+    // wave's prefetch pipeline seldom restarts at a class change)
+    int32_t w[kWaves + 1];
 };
 
 // Scalars of the iteration that live on the device (one per solve slot).

@@ -1192,6 +1192,182 @@ __device__ __forceinline__ void wg_block(const GradArgs& g, const Item& it, cons
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Workgroup-sized simplex (uniform weights) and box blocks on one wave each:
+// the block is streamed in steps of 64 U edges (the next step's loads in
+// flight while the current one is reduced), so no workgroup barrier is
+// needed and the eight waves of a workgroup work on different blocks.
+// Simplex blocks: one streaming pass gathers the sum of the positive t, the
+// two largest t and the edge of the largest; when the largest edge is the
+// only one above tau_0 = max(0, max t - gamma) (or the only positive one
+// when the sum is at most gamma) it is the whole active set and is added
+// from registers.  Otherwise the threshold iteration of the one-lane blocks
+// runs with one streaming pass per step, and a last pass adds the active
+// edges (as it does when x is written out).
+// ---------------------------------------------------------------------------
+template <typename VT, bool BOX, bool HASW, int U>
+struct WvRaw {
+    VT a[U], c[U];
+    int j[U];
+    float u[BOX ? U : 1];
+    float w[HASW ? U : 1];
+};
+template <int U, typename VT, bool BOX, bool HASW>
+__device__ __forceinline__ void wv_load(const GradArgs& g, const int64_t base, const int d, const int e0,
+                                        WvRaw<VT, BOX, HASW, U>& r)
+{
+    const VT* __restrict__ A = (const VT*)g.A + base;
+    const VT* __restrict__ C = (const VT*)g.C + base;
+    const int32_t* __restrict__ Dst = g.dst + base;
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int e = e0 + 64 * k + lane;
+        const uint32_t off = (uint32_t)(e < d ? e : d - 1);
+        r.a[k] = ldo(A, off);
+        r.c[k] = ldo(C, off);
+        r.j[k] = ldo(Dst, off);
+        if (BOX) r.u[k] = ldo(g.U + base, off);
+        if (HASW) r.w[k] = ldo(g.IV + base, off);
+    }
+}
+
+// one streaming pass over a block: f(e, t, a, c, j, u, wv) for every edge e
+template <int U, typename VT, bool CHECK, bool BOX, bool HASW, bool TAIL, typename F>
+__device__ __forceinline__ void wv_stream(const GradArgs& g, const Lds& s, const int64_t base, const int d, F&& f)
+{
+    using R = typename Val<VT>::reg;
+    const int lane = (int)(threadIdx.x & 63);
+    WvRaw<VT, BOX, HASW, U> cur;
+    wv_load<U>(g, base, d, 0, cur);
+#pragma unroll 1
+    for (int e0 = 0; e0 < d; e0 += 64 * U) {
+        WvRaw<VT, BOX, HASW, U> nxt;
+        double lam[U];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < U; ++k) lam[k] = get_lam<CHECK, TAIL>(s, g, cur.j[k]);
+        __builtin_amdgcn_sched_barrier(0);
+        // (the last step re-reads its own edges: in bounds, never used)
+        wv_load<U>(g, base, d, e0 + 64 * U < d ? e0 + 64 * U : e0, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int e = e0 + 64 * k + lane;
+            const R a = Val<VT>::cvt(cur.a[k]);
+            const R c = Val<VT>::cvt(cur.c[k]);
+            const double t = e < d ? -((double)c + (double)a * lam[k]) : -INFINITY;
+            f(e, t, a, c, cur.j[k], BOX ? cur.u[k] : 0.0f, HASW ? cur.w[k] : 1.0f);
+        }
+        cur = nxt;
+    }
+}
+
+template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
+__device__ __forceinline__ void wave_block(const GradArgs& g, const Item& it, const Lds& s, const double gamma,
+                                           Obj& ob)
+{
+    using R = typename Val<VT>::reg;
+    constexpr bool BOX = pj_proj(PJ) == 1;
+    constexpr bool DET = pj_det(PJ);
+    constexpr int U = sizeof(VT) == 8 ? 4 : 8;
+    static_assert(BOX || !HASW, "streamed simplex blocks have uniform weights");
+    const int d = uni(it.d);
+    const int64_t base = uni64(it.base);
+    const double inv_g = 1.0 / gamma;
+    // adds edge e's x (x != 0) to the objective parts and the row sums
+    auto add = [&](double t, double x, R a, R c, int j, float wv) {
+        const double q2 = HASW ? x * x / (double)wv : x * x;
+        ob.ot += t * x;
+        ob.oq += q2;
+        const double cx = CHECK ? (double)c * x : 0.0;
+        if (CHECK) ob.oc += cx;
+        accum<CHECK, TAIL, DET>(s, g, j, (double)a * x, cx, q2);
+    };
+    if constexpr (BOX) {
+        wv_stream<U, VT, CHECK, true, HASW, TAIL>(g, s, base, d, [&](int e, double t, R a, R c, int j, float u,
+                                                                     float wv) {
+            const double w = HASW ? (double)wv * inv_g : inv_g;
+            const double x = xval<true>(t, w, 0.0, u);
+            if (x != 0.0) add(t, x, a, c, j, wv);
+            if (g.X && e < d) g.X[g.perm[base + e]] = x;
+        });
+        return;
+    } else {
+        // pass 1: sum of positive t, two largest t, the largest edge's values
+        double sp = 0.0, m1 = -INFINITY, m2 = -INFINITY, at = 0.0;
+        R aa = 0, ac = 0;
+        int aj = 0;
+        wv_stream<U, VT, CHECK, false, false, TAIL>(g, s, base, d, [&](int, double t, R a, R c, int j, float,
+                                                                       float) {
+            sp += t > 0.0 ? t : 0.0;
+            const bool gt = t > m1;
+            m2 = gt ? m1 : fmax(m2, t);
+            m1 = gt ? t : m1;
+            at = gt ? t : at;
+            aa = gt ? a : aa;
+            ac = gt ? c : ac;
+            aj = gt ? j : aj;
+        });
+        const double lm1 = m1;
+        sp = wave_sum(sp);
+        wave_top2(m1, m2);
+        // the threshold, as on one-lane blocks of uniform weight
+        double tau = 0.0;
+        bool single = false;   // active set = the largest edge alone
+        if (sp > gamma) {
+            tau = m1 - gamma > 0.0 ? m1 - gamma : 0.0;
+            single = !(m2 > tau);
+        } else {
+            // sum of x = sum t+ / gamma <= 1: every positive t is active
+            single = !(m2 > 0.0);
+        }
+        if (sp > gamma && !single) {
+            double st = 0.0;
+            int n = 0;
+            wv_stream<U, VT, CHECK, false, false, TAIL>(g, s, base, d, [&](int, double t, R, R, int, float,
+                                                                           float) {
+                st += t > tau ? t : 0.0;
+                n += t > tau ? 1 : 0;
+            });
+            st = wave_sum(st);
+            n = grp_sum_i<64>(n);
+#pragma unroll 1
+            for (int rep = 0; rep < 2 * d + 4; ++rep) {
+                const double tn = (st - gamma) / (double)n;
+                double st2 = 0.0;
+                int n2 = 0;
+                wv_stream<U, VT, CHECK, false, false, TAIL>(g, s, base, d, [&](int, double t, R, R, int, float,
+                                                                               float) {
+                    st2 += t > tn ? t : 0.0;
+                    n2 += t > tn ? 1 : 0;
+                });
+                st2 = wave_sum(st2);
+                n2 = grp_sum_i<64>(n2);
+                tau = tn;
+                if (n2 >= n || n2 == 0) break;
+                st = st2;
+                n = n2;
+            }
+        }
+        if (single && !g.X) {
+            // the lane holding the largest t adds it (the first such lane)
+            const uint64_t m = __builtin_amdgcn_ballot_w64(lm1 == m1 && m1 > tau);
+            if (m != 0 && (int)(threadIdx.x & 63) == (int)__builtin_ctzll(m)) {
+                const double x = xval<false>(at, inv_g, tau, 0.0f);
+                if (x != 0.0) add(at, x, aa, ac, aj, 1.0f);
+            }
+            return;
+        }
+        wv_stream<U, VT, CHECK, false, false, TAIL>(g, s, base, d, [&](int e, double t, R a, R c, int j, float,
+                                                                       float) {
+            const double x = xval<false>(t, inv_g, tau, 0.0f);
+            if (x != 0.0) add(t, x, a, c, j, 1.0f);
+            if (g.X && e < d) g.X[g.perm[base + e]] = x;
+        });
+    }
+}
+
 // WG items of up to kWG * RW edges with the block in registers: edge
 // e = k kWG + tid, k < RW; all loads of a block issued at once, then the
 // threshold by workgroup reductions (every thread gets the same sums, so the
@@ -1321,6 +1497,27 @@ __device__ __forceinline__ void wg_project(const GradArgs& g, const Lds& s, cons
 
 __device__ __forceinline__ int wg_class(int d) { return d <= 2 * kWG ? 2 : d <= 4 * kWG ? 4 : 8; }
 
+// descriptor i of a WG item.  The item table is read-only while a kernel
+// runs: loading it through the constant address space, as four dwords (a
+// scalar load has no byte form), gives scalar loads, counted apart from the
+// vector memory operations, so reading a descriptor never waits for
+// outstanding prefetches or global atomics (a vector load of it would, its
+// value being needed in scalar registers).
+__device__ __forceinline__ Item wg_item(const GradArgs& g, const int i)
+{
+    typedef const __attribute__((address_space(4))) uint32_t CU32;
+    const CU32* p = (CU32*)(g.items + i);
+    const uint32_t w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3];
+    Item it;
+    it.base = (int64_t)(((uint64_t)w1 << 32) | w0);
+    it.d = (int32_t)w2;
+    it.nb = (uint8_t)(w3 & 0xFF);
+    it.lg = (uint8_t)((w3 >> 8) & 0xFF);
+    it.kind = (uint8_t)((w3 >> 16) & 0xFF);
+    it.proj = (uint8_t)(w3 >> 24);
+    return it;
+}
+
 // WG items i, i+1, ... of class RW and one projection type; returns the first
 // item not processed
 template <int RW, typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
@@ -1328,7 +1525,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
 {
     constexpr bool BOX = pj_proj(PJ) != 0;
     constexpr bool EARLY = !TAIL;   // lam from LDS
-    Item it = g.items[i];
+    Item it = wg_item(g, i);
     int64_t base = uni64(it.base);
     int d = uni(it.d);
     LaneRaw<VT, BOX, HASW, RW> cur;
@@ -1339,7 +1536,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
         int64_t bn = base;
         int dn = d;
         if (i + 1 < i1) {
-            const Item nx = g.items[i + 1];
+            const Item nx = wg_item(g, i + 1);
             const int nd = uni(nx.d);
             if (nx.proj == pj_proj(PJ) && nd <= 8 * kWG && wg_class(nd) == RW) {
                 more = true;
@@ -1379,7 +1576,7 @@ __device__ __forceinline__ int wg_run(const GradArgs& g, int i, const int i1, co
 // the fused gradient kernel: one workgroup per chunk
 // ---------------------------------------------------------------------------
 // lane items from batch entry r on; returns the first entry not processed
-template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ>
+template <typename VT, bool CHECK, bool HASW, bool TAIL, int PJ, bool ODD>
 __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine, const int r, const int rn,
                                              const Item& it, const Lds& s, double gamma, Obj& ob)
 {
@@ -1396,17 +1593,40 @@ __device__ __forceinline__ int lane_dispatch(const GradArgs& g, const Item& mine
     constexpr int CAP = pj_proj(PJ) == 2 ? (lane_cap(W8, HASW, TAIL) < kCutLaneCap ? lane_cap(W8, HASW, TAIL) : kCutLaneCap)
                                 : lane_cap(W8, HASW, TAIL);
     const int cls = lane_class<VT, HASW, TAIL>(it.d, it.lg);
-    if (it.lg == 2) {
+    // blocks on S = 2^lg lanes: the host picks the S that pads a block's
+    // degree least (S times the row class) among lg = 1..6 for the ordinary
+    // kernels (ODD), among lg = 2, 4, 6 for those of problems with capped
+    // blocks or in deterministic mode (their code stays smaller)
+    switch (it.lg) {
+    case 1:
+        if constexpr (ODD) {
+            if (cls == 8) return lane_run<2, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
+            return lane_run<2, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
+        }
+        break;
+    case 2:
         if (cls == 8) return lane_run<4, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
         return lane_run<4, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
-    }
-    if (it.lg == 4) {
+    case 3:
+        if constexpr (ODD) {
+            if (cls == 8) return lane_run<8, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
+            return lane_run<8, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
+        }
+        break;
+    case 4:
         if (cls == 8) return lane_run<16, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
         return lane_run<16, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
-    }
-    if (it.lg == 6) {
+    case 5:
+        if constexpr (ODD) {
+            if (cls == 8) return lane_run<32, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
+            return lane_run<32, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
+        }
+        break;
+    case 6:
         if (cls == 8) return lane_run<64, VT, CHECK, HASW, TAIL, PJ, 8>(g, mine, r, rn, s, gamma, ob);
         return lane_run<64, VT, CHECK, HASW, TAIL, PJ, RMAX>(g, mine, r, rn, s, gamma, ob);
+    default:
+        break;
     }
     switch (cls) {
     case 4: return lane_run<1, VT, CHECK, HASW, TAIL, PJ, 4>(g, mine, r, rn, s, gamma, ob);
@@ -1492,35 +1712,55 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     const Chunk ch = g.chunks[chunk];
     Obj ob = {0.0, 0.0, 0.0};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // this chunk's share of the lane items: a wave takes items a0 + wave +
-    // r*kWaves; their descriptors arrive 64 at a time (lane r holds item r of
-    // the batch) and are broadcast with readlane, so a group waits on its
-    // data only
+    // this wave's share of the chunk's lane items, a contiguous range (read
+    // with scalar loads); their descriptors arrive 64 at a time (lane r holds
+    // item r of the batch) and are broadcast with readlane, so a group waits
+    // on its data only
     {
-        const int i0 = ch.a0, i1 = ch.a1;
-        const int nmine = i1 - i0 > wave ? (i1 - i0 - wave + kWaves - 1) / kWaves : 0;
+        typedef const __attribute__((address_space(4))) int32_t CI32;
+        const CI32* wb = (CI32*)&g.chunks[chunk].w[0];
+        const int i0 = wb[wave], i1 = wb[wave + 1];
+        const int nmine = i1 - i0;
         for (int r0 = 0; r0 < nmine; r0 += 64) {
             const int lane = threadIdx.x & 63;
-            const int my = i0 + wave + (r0 + lane) * kWaves;
+            const int my = i0 + r0 + lane;
             Item mine = {0, 0, 0, 0, 0, 0};
             if (r0 + lane < nmine) mine = g.items[my];
             const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
             for (int r = 0; r < rn;) {
                 const Item it = item_at(mine, r);
+                constexpr bool ODD = !CUT && !DET;
                 if (it.proj == 1) {
-                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 1 | D4>(g, mine, r, rn, it, s, gamma, ob);
+                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 1 | D4, ODD>(g, mine, r, rn, it, s, gamma, ob);
                 } else if (it.proj == 2) {
                     // capped blocks exist only in problems launched with CUT
-                    if constexpr (CUT) r = lane_dispatch<VT, CHECK, HASW, TAIL, 2 | D4>(g, mine, r, rn, it, s, gamma, ob);
+                    if constexpr (CUT)
+                        r = lane_dispatch<VT, CHECK, HASW, TAIL, 2 | D4, ODD>(g, mine, r, rn, it, s, gamma, ob);
                     else r = rn;
                 } else {
-                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 0 | D4>(g, mine, r, rn, it, s, gamma, ob);
+                    r = lane_dispatch<VT, CHECK, HASW, TAIL, 0 | D4, ODD>(g, mine, r, rn, it, s, gamma, ob);
                 }
             }
         }
     }
+    // WG items of box blocks and of simplex blocks with uniform weights: one
+    // wave per block, the waves independent (items wave, wave + kWaves, ...)
+    auto streamed = [&](const Item& it) { return it.proj == 1 || (it.proj == 0 && !HASW); };
+    for (int i = ch.b0 + wave; i < ch.b1; i += kWaves) {
+        const Item it = wg_item(g, i);
+        if (it.proj == 1) wave_block<VT, CHECK, HASW, TAIL, 1 | D4>(g, it, s, gamma, ob);
+        else if constexpr (!HASW) {
+            if (it.proj == 0) wave_block<VT, CHECK, false, TAIL, 0 | D4>(g, it, s, gamma, ob);
+        }
+    }
+    // the others (capped blocks, simplex blocks with per-edge weights) on the
+    // whole workgroup
     for (int i = ch.b0; i < ch.b1;) {
-        const Item it = g.items[i];
+        const Item it = wg_item(g, i);
+        if (streamed(it)) {
+            ++i;
+            continue;
+        }
         const int d = uni(it.d);
         if (d > 8 * kWG) {
             if (it.proj == 1) wg_block<VT, CHECK, HASW, TAIL, 1 | D4>(g, it, s, gamma, ob);
