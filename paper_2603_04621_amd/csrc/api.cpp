@@ -383,15 +383,36 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
             r[1] = (int32_t)L.items.size();
         }
     }
-    // waves' shares of each chunk's lane items: contiguous, split at equal
-    // cost (rows of the group's register class, plus a fixed part)
+    // waves' shares of each chunk's lane items.  With few classes (kernel
+    // paths: lanes per block, register rows, projection) a wave takes every
+    // kWaves-th item (w[0] = -1): the shares balance by themselves and each
+    // wave meets every class once.  With many classes a wave takes a
+    // contiguous share, split at equal estimated cost (rows of the group's
+    // register class, plus a fixed part), so that it meets only a few classes
+    // (each class change restarts the wave's prefetch pipeline).
+    auto item_class = [&](const Item& it) -> int {
+        const int64_t R = ((int64_t)it.d + (1 << it.lg) - 1) >> it.lg;
+        const int rows = it.lg == 0 ? (it.d <= 4 ? 4 : it.d <= 8 ? 8 : it.d <= 12 ? 12 : it.d <= 16 ? 16
+                                                                                     : it.d <= 24 ? 24 : 32)
+                                    : (R <= 8 ? 8 : pmax);
+        return (it.lg * 64 + rows) * 4 + it.proj;
+    };
+    std::vector<int> classes;
+    for (const Item& it : L.items)
+        if (it.kind == ITEM_LANE) classes.push_back(item_class(it));
+    std::sort(classes.begin(), classes.end());
+    const bool strided = std::unique(classes.begin(), classes.end()) - classes.begin() <= kStridedClasses;
     auto item_cost = [&](const Item& it) -> int64_t {
         int64_t rows;
         if (it.lg == 0) rows = it.d <= 4 ? 4 : it.d <= 8 ? 8 : it.d <= 12 ? 12 : it.d <= 16 ? 16 : it.d <= 24 ? 24 : 32;
         else rows = (((int64_t)it.d + (1 << it.lg) - 1) >> it.lg) <= 8 ? 8 : pmax;
         return rows + 4;
     };
-    for (int c = 0; c < nchunks; ++c) {
+    for (int c = 0; c < nchunks && strided; ++c) {
+        Chunk& ch = L.chunks[c];
+        for (int q = 0; q <= kWaves; ++q) ch.w[q] = -1;
+    }
+    for (int c = 0; c < nchunks && !strided; ++c) {
         Chunk& ch = L.chunks[c];
         int64_t tot = 0;
         for (int32_t q = ch.a0; q < ch.a1; ++q) tot += item_cost(L.items[q]);

@@ -83,9 +83,12 @@ struct Chunk {               // lane items [a0, a1), workgroup blocks [b0, b1)
     int32_t a0, a1, b0, b1;
     // lane items of wave q of the one-entry kernels: [w[q], w[q + 1]), a
     // contiguous share of [a0, a1) (items of one class stay together, so a
-    // wave's prefetch pipeline seldom restarts at a class change)
+    // wave's prefetch pipeline seldom restarts at a class change); w[0] < 0:
+    // items a0 + q, a0 + q + kWaves, ... instead
     int32_t w[kWaves + 1];
 };
+// layouts with at most this many lane-item classes use the strided shares
+constexpr int kStridedClasses = 12;
 
 // Scalars of the iteration that live on the device (one per solve slot).
 struct SolveState {

@@ -1712,18 +1712,21 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
     const Chunk ch = g.chunks[chunk];
     Obj ob = {0.0, 0.0, 0.0};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // this wave's share of the chunk's lane items, a contiguous range (read
-    // with scalar loads); their descriptors arrive 64 at a time (lane r holds
-    // item r of the batch) and are broadcast with readlane, so a group waits
-    // on its data only
+    // this wave's share of the chunk's lane items (bounds read with scalar
+    // loads); their descriptors arrive 64 at a time (lane r holds item r of
+    // the batch) and are broadcast with readlane, so a group waits on its
+    // data only
     {
         typedef const __attribute__((address_space(4))) int32_t CI32;
         const CI32* wb = (CI32*)&g.chunks[chunk].w[0];
-        const int i0 = wb[wave], i1 = wb[wave + 1];
-        const int nmine = i1 - i0;
+        const bool strided = wb[0] < 0;
+        const int i0 = strided ? ch.a0 + wave : wb[wave];
+        const int step = strided ? kWaves : 1;
+        const int nmine = strided ? (ch.a1 - ch.a0 > wave ? (ch.a1 - ch.a0 - wave + kWaves - 1) / kWaves : 0)
+                                  : wb[wave + 1] - i0;
         for (int r0 = 0; r0 < nmine; r0 += 64) {
             const int lane = threadIdx.x & 63;
-            const int my = i0 + r0 + lane;
+            const int my = i0 + (r0 + lane) * step;
             Item mine = {0, 0, 0, 0, 0, 0};
             if (r0 + lane < nmine) mine = g.items[my];
             const int rn = nmine - r0 < 64 ? nmine - r0 : 64;
