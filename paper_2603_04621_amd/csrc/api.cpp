@@ -266,10 +266,10 @@ struct HostLayout {
 // block) from wgmin edges on (wgmin > 0); else, among S = 2^lg (lg = 1..6,
 // or 2, 4, 6 when even) with R = ceil(d / S) <= rmax rows per lane, the S
 // whose register rows pad the block least: the kernel holds R rows in a
-// class of 8 rows (R <= 8) or of pmax rows, so a group costs S times the
-// class in row slots (the smaller S on ties: fewer reduction steps); -1 for
-// longer blocks.
-static int block_lg(int64_t d, int cap, int rmax, int pmax, bool even, int wgmin)
+// class of 4 rows (R <= 4, when p4: the multi-entry kernel), 8 rows (R <= 8)
+// or pmax rows, so a group costs S times the class in row slots (the smaller
+// S on ties: fewer reduction steps); -1 for longer blocks.
+static int block_lg(int64_t d, int cap, int rmax, int pmax, bool even, int wgmin, bool p4)
 {
     if (d <= cap) return 0;
     if (wgmin > 0 && d >= wgmin) return -1;
@@ -278,7 +278,7 @@ static int block_lg(int64_t d, int cap, int rmax, int pmax, bool even, int wgmin
     for (int lg = even ? 2 : 1; lg <= 6; lg += even ? 2 : 1) {
         const int64_t R = (d + (1 << lg) - 1) >> lg;
         if (R > rmax) continue;
-        const int64_t slots = ((int64_t)1 << lg) * (R <= 8 ? 8 : pmax);
+        const int64_t slots = ((int64_t)1 << lg) * (p4 && R <= 4 ? 4 : R <= 8 ? 8 : pmax);
         if (best < 0 || slots < best_slots) {
             best = lg;
             best_slots = slots;
@@ -295,7 +295,7 @@ static int block_lg(int64_t d, int cap, int rmax, int pmax, bool even, int wgmin
 // the deal reversed every round) and lays the stream out chunk by chunk, so
 // each workgroup reads one contiguous region per kind.
 static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax, int pmax, bool even, int wgmin,
-                        HostLayout& L)
+                        bool p4, HostLayout& L)
 {
     const int64_t I = d->num_blocks;
     const int64_t dmax_lane = std::max<int64_t>(cap, 64 * (int64_t)rmax);
@@ -313,8 +313,8 @@ static void build_items(const dl_problem_desc* d, int nchunks, int cap, int rmax
         // capped-simplex blocks: smaller one-lane and per-lane classes
         const int lg = pr == DL_PROJ_CAPPED
                            ? block_lg(deg, std::min(cap, kCutLaneCap), std::min(rmax, kCutRmax),
-                                      std::min(pmax, kCutRmax), even, wgmin)
-                           : block_lg(deg, cap, rmax, pmax, even, wgmin);
+                                      std::min(pmax, kCutRmax), even, wgmin, p4)
+                           : block_lg(deg, cap, rmax, pmax, even, wgmin, p4);
         if (lg >= 0) bucket(lg, pr, deg).push_back(i);
         else wgb.push_back({(int64_t)pr, i});
     }
@@ -644,11 +644,21 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
             rdeg[rf] += 1;
         }
     }
+    // a plane whose entry is present in every column with one row (a dense
+    // row such as the count row): its sums are combined per wave in the
+    // multi-entry kernel instead of one LDS atomic per active edge
+    for (int f = 0; f < nf && nf > 1 && p->dense_f < 0 && n > 0; ++f) {
+        bool same = true;
+        for (int64_t e = 0; e < n && same; ++e)
+            same = ccount[e] > f && crow[(size_t)f * n + e] == crow[(size_t)f * n];
+        if (same) p->dense_f = f;
+    }
     // relabel rows by descending degree (ties by index): hot rows first
     std::vector<int32_t> orig((size_t)m), newid((size_t)m);
     std::iota(orig.begin(), orig.end(), 0);
     std::stable_sort(orig.begin(), orig.end(), [&](int32_t a, int32_t b) { return rdeg[a] > rdeg[b]; });
     for (int64_t j = 0; j < m; ++j) newid[orig[j]] = (int32_t)j;
+    if (p->dense_f >= 0) p->dense_row = newid[crow[(size_t)p->dense_f * n]];
     std::vector<double> bD((size_t)m), Dv((size_t)m);
     for (int64_t j = 0; j < m; ++j) {
         const int32_t o = orig[j];
@@ -702,10 +712,10 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     // a threshold beyond what 64-lane segments hold changes nothing
     p->wg_min = lc.wg_min > 0 && lc.wg_min <= 64 * p->seg_rmax ? std::max(lc.wg_min, p->lane_cap + 1) : 0;
     // the kernel variant's largest row class; segments of 4, 16 or 64 lanes
-    // only for the multi-entry kernel and for the kernels of problems with
-    // capped blocks or in deterministic mode
+    // only for the kernels of problems with capped blocks or in
+    // deterministic mode; the multi-entry kernel also has a 4-row class
     const int pmax = nf > 1 ? kMfRmax : seg_rmax(f64, p->has_w != 0, tail);
-    build_items(d, nch, p->lane_cap, p->seg_rmax, pmax, nf > 1 || p->has_cut || p->det, p->wg_min, L);
+    build_items(d, nch, p->lane_cap, p->seg_rmax, pmax, nf == 1 && (p->has_cut || p->det), p->wg_min, nf > 1, L);
     p->nchunks = nch;
     p->nitems = (int)L.items.size();
     p->n_lane = L.n_lane;
@@ -1144,6 +1154,8 @@ GradArgs grad_args(const dl_problem* p, const double* lam, const double* gamma_p
         g.dst2[f] = p->dst2[f];
     }
     g.restore = 0;
+    g.dense_f = p->dense_f;
+    g.dense_row = p->dense_row;
     g.srow = p->srow;
     g.corr_part = p->corr_part;
     return g;

@@ -11,9 +11,11 @@
 //   (simplex, box or capped simplex, the thresholds of the one-family
 //   kernel), and a_f x_e added to row r_f for every f.
 // Rows are relabelled by degree, so a dense row (present in every column) is
-// row 0 and lives in LDS.  Work items are the one-family layout's, with at
-// most kMfLaneCap edges on one lane and kMfRmax rows per lane (the planes
-// multiply the registers per edge); longer blocks take one workgroup that
+// row 0 and lives in LDS; its plane's terms are summed per lane and added
+// once per wave.  Work items are the one-family layout's, with at most
+// kMfLaneCap edges on one lane and kMfRmax rows per lane (the planes
+// multiply the registers per edge), segments on 2..64 lanes with register
+// classes of 4 or kMfRmax rows; longer blocks take one workgroup that
 // re-reads the block from L2 on every pass of its threshold.
 //
 // Restore mode (g.restore = 1, on gap-check iterations after the reduction
@@ -51,7 +53,7 @@ __device__ __forceinline__ double mf_tau(const double (&t)[P], const float (&u)[
 // one LANE group: loads, t, threshold, then row sums (or the restoration)
 template <int S, int P, int PJ, typename VT, bool HASW, bool TAIL>
 __device__ __forceinline__ void mf_lane_group(const GradArgs& g, const Item& it, const Lds& s, double gamma,
-                                              Obj& ob, double& corr)
+                                              Obj& ob, double& corr, double& dacc)
 {
     constexpr bool BOX = PJ != 0;
     const SegGeo q = seg_geo<S>(it);
@@ -105,7 +107,8 @@ __device__ __forceinline__ void mf_lane_group(const GradArgs& g, const Item& it,
 #pragma unroll
                 for (int f = 0; f < kMfPlanes; ++f) {
                     const double af = (double)Val<VT>::cvt(a[f][k]);
-                    if (f < nf && af != 0.0) accum<false, TAIL, false>(s, g, r[f][k], af * x, 0.0, 0.0);
+                    if (f == g.dense_f) dacc += af * x;
+                    else if (f < nf && af != 0.0) accum<false, TAIL, false>(s, g, r[f][k], af * x, 0.0, 0.0);
                 }
             } else {
                 double se = 1.0;
@@ -142,7 +145,7 @@ __device__ __forceinline__ double mf_edge_t(const GradArgs& g, const Lds& s, int
 // stays in L2 between passes)
 template <int PJ, typename VT, bool HASW, bool TAIL>
 __device__ __forceinline__ void mf_wg_block(const GradArgs& g, const Item& it, const Lds& s, double gamma,
-                                            Obj& ob, double& corr)
+                                            Obj& ob, double& corr, double& dacc)
 {
     constexpr bool BOX = PJ != 0;
     const int d = uni(it.d);
@@ -215,7 +218,8 @@ __device__ __forceinline__ void mf_wg_block(const GradArgs& g, const Item& it, c
                 ob.oc += cx;
                 for (int f = 0; f < g.nf; ++f) {
                     const double af = (double)Val<VT>::ld(mf_a<VT>(g, f), idx);
-                    if (af != 0.0) accum<false, TAIL, false>(s, g, mf_r(g, f)[idx], af * x, 0.0, 0.0);
+                    if (f == g.dense_f) dacc += af * x;
+                    else if (af != 0.0) accum<false, TAIL, false>(s, g, mf_r(g, f)[idx], af * x, 0.0, 0.0);
                 }
             } else {
                 double se = 1.0;
@@ -229,19 +233,30 @@ __device__ __forceinline__ void mf_wg_block(const GradArgs& g, const Item& it, c
     __syncthreads();
 }
 
+// lanes per block S = 2^lg (the host picks the S that pads the degree least)
+// and a register class of 4 or kMfRmax rows per lane
+template <int S, int PJ, typename VT, bool HASW, bool TAIL>
+__device__ __forceinline__ void mf_seg(const GradArgs& g, const Item& it, const Lds& s, double gamma, Obj& ob,
+                                       double& corr, double& dacc)
+{
+    if ((it.d + S - 1) / S <= 4) mf_lane_group<S, 4, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+    else mf_lane_group<S, kMfRmax, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+}
 template <int PJ, typename VT, bool HASW, bool TAIL>
 __device__ __forceinline__ void mf_lane_dispatch(const GradArgs& g, const Item& it, const Lds& s, double gamma,
-                                                 Obj& ob, double& corr)
+                                                 Obj& ob, double& corr, double& dacc)
 {
-    if (it.lg == 0) {
-        if (it.d <= 4) mf_lane_group<1, 4, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-        else mf_lane_group<1, kMfLaneCap, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-    } else if (it.lg == 2) {
-        mf_lane_group<4, kMfRmax, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-    } else if (it.lg == 4) {
-        mf_lane_group<16, kMfRmax, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-    } else {
-        mf_lane_group<64, kMfRmax, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
+    switch (it.lg) {
+    case 0:
+        if (it.d <= 4) mf_lane_group<1, 4, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+        else mf_lane_group<1, kMfLaneCap, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+        break;
+    case 1: mf_seg<2, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc); break;
+    case 2: mf_seg<4, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc); break;
+    case 3: mf_seg<8, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc); break;
+    case 4: mf_seg<16, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc); break;
+    case 5: mf_seg<32, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc); break;
+    default: mf_seg<64, PJ, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc); break;
     }
 }
 
@@ -270,20 +285,28 @@ __global__ __launch_bounds__(kWG) void grad_mf_kernel(GradArgs g)
     const Chunk ch = g.chunks[chunk];
     Obj ob = {0.0, 0.0, 0.0};
     double corr = 0.0;
+    // the dense plane's a x, summed per lane and added once per wave
+    double dacc = 0.0;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // (descriptors by scalar loads: reading one never waits for the vector
+    // memory operations in flight)
     for (int i = ch.a0 + wave; i < ch.a1; i += kWaves) {
-        Item it = g.items[i];
+        Item it = wg_item(g, i);
         it.base = uni64(it.base);
         it.d = uni(it.d);
-        if (it.proj == 1) mf_lane_dispatch<1, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-        else if (it.proj == 2) mf_lane_dispatch<2, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-        else mf_lane_dispatch<0, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
+        if (it.proj == 1) mf_lane_dispatch<1, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+        else if (it.proj == 2) mf_lane_dispatch<2, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+        else mf_lane_dispatch<0, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
     }
     for (int i = ch.b0; i < ch.b1; ++i) {
-        const Item it = g.items[i];
-        if (it.proj == 1) mf_wg_block<1, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-        else if (it.proj == 2) mf_wg_block<2, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
-        else mf_wg_block<0, VT, HASW, TAIL>(g, it, s, gamma, ob, corr);
+        const Item it = wg_item(g, i);
+        if (it.proj == 1) mf_wg_block<1, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+        else if (it.proj == 2) mf_wg_block<2, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+        else mf_wg_block<0, VT, HASW, TAIL>(g, it, s, gamma, ob, corr, dacc);
+    }
+    if (g.dense_f >= 0 && !g.restore) {
+        dacc = wave_sum(dacc);
+        if ((threadIdx.x & 63) == 0 && dacc != 0.0) accum<false, TAIL, false>(s, g, g.dense_row, dacc, 0.0, 0.0);
     }
     __syncthreads();
 

@@ -38,6 +38,9 @@ struct GradArgs {
     const int32_t* dst2[kMfPlanes - 1];
     int32_t nf;              // entries per column (1: the one-family kernels)
     int32_t restore;         // restoration pass of the gap (see grad_mf.hpp)
+    int32_t dense_f;         // plane whose row is the same for every column (a dense
+                             // row such as the count row), -1: none
+    int32_t dense_row;       // that row (internal order)
     const double* srow;      // [J] min(1, b_j / (A x)_j), internal row order
     double* corr_part;       // [nchunks] restoration correction of P
 };

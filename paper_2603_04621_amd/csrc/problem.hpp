@@ -16,6 +16,7 @@ struct dl_problem {
     int has_box = 0, has_w = 0, solve_ok = 1;
     int has_cut = 0;                   // some block is a capped simplex
     int nf = 1;                        // entries per column (several families, dense rows)
+    int dense_f = -1, dense_row = 0;   // plane holding one row for every column, and that row
     void* A2[dl::kMfPlanes - 1] = {};  // planes 1..nf-1 of the coefficients
     int32_t* dst2[dl::kMfPlanes - 1] = {};   // and their rows (internal order)
     double* srow = nullptr;            // [J] restoration ratios (nf > 1)
