@@ -60,9 +60,18 @@ def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc
         grad, x, e = p.dual_grad(torch.from_numpy(lam), gamma, want_x=True, want_eval=True)
         grad = grad.cpu().numpy()
         x = x.cpu().numpy()
+        # the same evaluation without x (the solve's form: some paths, such
+        # as wave-streamed blocks with one active edge, skip work when x is
+        # not written)
+        grad_nx, _, e_nx = p.dual_grad(torch.from_numpy(lam), gamma, want_x=False, want_eval=True)
+        grad_nx = grad_nx.cpu().numpy()
     scale = np.bincount(inst.dst, weights=np.abs(ref_inst.a * ev.x), minlength=inst.m) + np.abs(inst.b)
     gerr = np.abs(grad - ev.grad) / np.maximum(scale, 1e-300)
     gerr[(scale == 0) & (grad == ev.grad)] = 0.0
+    gerr_nx = np.abs(grad_nx - ev.grad) / np.maximum(scale, 1e-300)
+    gerr_nx[(scale == 0) & (grad_nx == ev.grad)] = 0.0
+    assert (gerr_nx.max() if gerr_nx.size else 0.0) <= grad_tol, float(gerr_nx.max())
+    assert abs(e_nx["g"] - ev.g) / max(1.0, abs(ev.g)) <= g_tol, (e_nx["g"], ev.g)
     v2 = vv ** 2 if vv is not None else 1.0
     pmag = float(np.sum(np.abs(ref_inst.c * ev.x)) + 0.5 * gamma * np.sum(v2 * ev.x ** 2))
     out = {"grad": float(gerr.max()) if gerr.size else 0.0,
@@ -77,6 +86,7 @@ def compare(O, inst, storage, lam, gamma, grad_tol=1e-5, g_tol=1e-6, layout="csc
     assert out["grad"] <= grad_tol, out
     assert out["g"] <= g_tol, out
     assert out["P"] <= 1e-6, out
+    assert abs(e_nx["P"] - ev.P) / max(1.0, pmag) <= 1e-6, (e_nx["P"], ev.P)
     assert_x_close(ref_inst, lam, gamma, vv if v_dev is None else v_dev, ev.x, x)
     check_active_sets(ref_inst, ev.x, x)
     return out
