@@ -232,22 +232,29 @@ extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, con
                               p->yp, p->G, p->Gp, p->lam_eval, s),
             "init kernel");
     }
-    dlh::BatchRunner br;
-    st = br.build(ps, prms, s);
+    // br_all: the tables of every problem (done count, final states);
+    // iterations run on the tables of the problems still running, rebuilt
+    // (and the graph captured again) whenever a quarter of them have
+    // stopped, so that stopped problems no longer occupy the launches
+    dlh::BatchRunner br_all, br_act;
+    st = br_all.build(ps, prms, s);
     if (st != DL_OK) return st;
+    dlh::BatchRunner* br = &br_all;
+    int nact = count;
     const int64_t N = o->max_iters;
     int64_t seg = o->graph_iters > 0 ? o->graph_iters : (o->check_every > 0 ? o->check_every : 16);
     if (o->check_every > 0 && seg % o->check_every != 0) seg = o->check_every;
     int64_t k = 0;
     bool all_done = false;
     const int64_t nfull = N / seg;
-    if (nfull > 0) {
+    int64_t gi = 0;
+    while (gi < nfull && !all_done) {
         GraphHolder gh;
         TRY(hipStreamCreateWithFlags(&gh.cap, hipStreamNonBlocking), "capture stream");
         TRY(hipStreamBeginCapture(gh.cap, hipStreamCaptureModeThreadLocal), "begin capture");
         for (int64_t q = 0; q < seg; ++q) {
             const int check = o->check_every > 0 && (q + 1) % o->check_every == 0;
-            hipError_t e = br.enqueue_iteration(check, gh.cap);
+            hipError_t e = br->enqueue_iteration(check, gh.cap);
             if (e != hipSuccess) {
                 hipGraph_t gtmp = nullptr;
                 (void)hipStreamEndCapture(gh.cap, &gtmp);
@@ -257,30 +264,48 @@ extern "C" dl_status dl_batch_solve(dl_problem* const* probs, int32_t count, con
         }
         TRY(hipStreamEndCapture(gh.cap, &gh.graph), "end capture");
         TRY(hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0), "instantiate graph");
-        for (int64_t gi = 0; gi < nfull; ++gi) {
+        bool rebuild = false;
+        for (; gi < nfull && !rebuild; ++gi) {
             TRY(hipGraphLaunch(gh.exec, s), "graph launch");
             k += seg;
             // poll every few replays (the check itself waits for the stream)
             if ((gi & 3) == 3 || gi == nfull - 1) {
                 int nd = 0;
-                TRY(br.count_done(s, &nd), "poll");
+                TRY(br_all.count_done(s, &nd), "poll");
                 if (nd == count) {
                     all_done = true;
+                    ++gi;
                     break;
                 }
+                rebuild = 4 * (count - nd) <= 3 * nact;
             }
+        }
+        if (rebuild) {
+            std::vector<SolveState> fs;
+            TRY(br_all.states(s, fs), "read states");
+            std::vector<dl_problem*> act;
+            std::vector<SolveParams> aprm;
+            for (int q = 0; q < count; ++q)
+                if (!fs[q].done) {
+                    act.push_back(ps[q]);
+                    aprm.push_back(prms[(size_t)q]);
+                }
+            st = br_act.build(act, aprm, s);
+            if (st != DL_OK) return st;
+            br = &br_act;
+            nact = (int)act.size();
         }
     }
     // the remainder of max_iters that fills no whole graph (none once every
     // problem has stopped)
     for (; k < N && !all_done; ++k)
-        TRY(br.enqueue_iteration(dlh::is_check_iter(o, k) ? 1 : 0, s), "batch iteration");
+        TRY(br->enqueue_iteration(dlh::is_check_iter(o, k) ? 1 : 0, s), "batch iteration");
     for (int q = 0; q < count; ++q) {
         dl_problem* p = ps[q];
         TRY(launch_solve_final(p->st, p->y, p->yp, p->orig, p->D, p->J, lambdas[q], s), "final kernel");
     }
     std::vector<SolveState> fs;
-    TRY(br.states(s, fs), "read states");
+    TRY(br_all.states(s, fs), "read states");
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     dl_status worst = DL_OK;
     for (int q = 0; q < count; ++q) {
