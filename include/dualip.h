@@ -136,8 +136,10 @@ typedef struct {
  *                  from a bound on the largest row sum, so that no row can
  *                  overflow 2^60) and added with integer atomics, which are
  *                  order-independent: dl_dual_grad and dl_solve return the same
- *                  bits on every run.  Costs LDS (16 instead of 12 bytes per
- *                  row kept in LDS) and integer conversions per term.
+ *                  bits on every run.  Costs integer conversions per term,
+ *                  and LDS (16 bytes per row kept in LDS in every pass, where
+ *                  otherwise problems with more rows than fit at 16 bytes
+ *                  keep 12).
  *   lane_cap, seg_rmax, wg_min, chunks_per_cu
  *                  the work layout by hand (0 = the default of each; the
  *                  starting point of autotune when it is on): largest degree

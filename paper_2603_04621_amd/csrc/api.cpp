@@ -686,9 +686,15 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     int nch = (int)std::min<int64_t>((int64_t)cus * lc.chunk_mult, std::max<int64_t>(1, (n + 32767) / 32768));
     HostLayout L;
     const size_t max_lds = device_max_lds(p->device);
-    // bytes of one LDS sum: f32, or a 64-bit integer in deterministic mode
+    // bytes of one LDS sum in gap-check passes: f32, or a 64-bit integer in
+    // deterministic mode.  Ordinary passes hold lam and the a x sum per row:
+    // 8 bytes (FP64) when every row fits at 16 bytes, else f32 for the K rows
+    // that fit at 12 (deterministic mode: the 64-bit integer, 16 bytes).
+    // Problems with more rows than fit at 16 bytes but no more than fit at
+    // 12 keep the 16-byte capacity and their coldest rows beyond it.
     const int64_t hes = p->det ? 8 : 4, lds_free = (int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double);
-    int64_t kmax = lds_free / (8 + hes);
+    const int64_t kwide = lds_free / 16, knarrow = p->det ? kwide : lds_free / 12;
+    int64_t kmax = m <= kwide ? m : (m > knarrow ? knarrow : kwide);
     p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
     const bool f64 = opts.storage == DL_F64, tail = p->K < m;
     // check passes: without tail rows the c x and v^2 x^2 sums of the first

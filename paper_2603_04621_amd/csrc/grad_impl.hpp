@@ -98,6 +98,8 @@ struct Lds {
     float* hg;     // [K] sum a x
     float* hc;     // [K] sum c x   (check passes)
     float* hq;     // [K] sum v^2 x^2 (check passes)
+    double* hgd;   // [K] sum a x in FP64 (ordinary passes without rows beyond K,
+                   // outside deterministic mode)
 };
 
 // three sums and a count over the whole workgroup (all threads call it)
@@ -237,7 +239,12 @@ __device__ __forceinline__ void gl_term(const GradArgs& g, double* p, double v, 
 template <bool CHECK, bool TAIL, bool DET>
 __device__ __forceinline__ void accum_lds(const Lds& s, const GradArgs& g, int j, double ax, double cx, double q)
 {
-    lds_term<DET>(g, s.hg, j, ax, 0);
+    // ordinary passes of problems whose rows all fit in LDS at 16 bytes add
+    // a x in FP64 (the LDS's f32 atomic add runs at a fraction of the rate
+    // of its FP64 and integer ones: box blocks, whose active edges are most
+    // of their edges, ran 1.5x slower with it)
+    if constexpr (!CHECK && !DET && !TAIL) __hip_atomic_fetch_add(s.hgd + j, ax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else lds_term<DET>(g, s.hg, j, ax, 0);
     if (CHECK) {
         if (j < g.Kc) {
             lds_term<DET>(g, s.hc, j, cx, 1);
@@ -1669,8 +1676,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
         s.lam = (double*)p;
         p += (size_t)K * sizeof(double);
     }
+    // ordinary passes of problems without rows beyond LDS (outside
+    // deterministic mode) keep the a x sums in FP64
+    constexpr bool WIDE = !CHECK && !DET && !TAIL;
     s.hg = (float*)p;
-    p += (size_t)K * es;
+    s.hgd = WIDE ? (double*)p : nullptr;
+    p += (size_t)K * (WIDE ? sizeof(double) : es);
     s.hc = s.hq = nullptr;
     if (CHECK) {
         s.hc = (float*)p;
@@ -1698,6 +1709,8 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
                     ((unsigned long long*)s.hc)[j] = 0ull;
                     ((unsigned long long*)s.hq)[j] = 0ull;
                 }
+        } else if constexpr (WIDE) {
+            for (j = threadIdx.x; j < K; j += kWG) s.hgd[j] = 0.0;
         } else {
             for (j = threadIdx.x; j < K; j += kWG) s.hg[j] = 0.0f;
             if (CHECK)
@@ -1805,7 +1818,10 @@ __device__ __forceinline__ void grad_body(const GradArgs& g, const int chunk)
             }
     } else {
         float* row = g.part + (int64_t)chunk * K;
-        for (int j = threadIdx.x; j < K; j += kWG) row[j] = s.hg[j];
+        if constexpr (WIDE)
+            for (int j = threadIdx.x; j < K; j += kWG) row[j] = (float)s.hgd[j];
+        else
+            for (int j = threadIdx.x; j < K; j += kWG) row[j] = s.hg[j];
         if (CHECK)
             for (int j = threadIdx.x; j < KC; j += kWG) {
                 row[plane + j] = s.hc[j];

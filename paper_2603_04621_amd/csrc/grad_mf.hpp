@@ -273,12 +273,16 @@ __global__ __launch_bounds__(kWG) void grad_mf_kernel(GradArgs g)
     const int K = g.K;
     s.lam = (double*)p;
     p += (size_t)K * sizeof(double);
+    // the a x sums: FP64 without rows beyond K (as in the one-entry kernels'
+    // ordinary passes), else f32
     s.hg = (float*)p;
+    s.hgd = TAIL ? nullptr : (double*)p;
     s.hc = s.hq = nullptr;
     const double gamma = g.gamma_ptr ? *g.gamma_ptr : g.gamma_val;
     for (int j = threadIdx.x; j < K; j += kWG) {
         s.lam[j] = g.lam[j];
-        s.hg[j] = 0.0f;
+        if constexpr (TAIL) s.hg[j] = 0.0f;
+        else s.hgd[j] = 0.0;
     }
     __syncthreads();
 
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(kWG) void grad_mf_kernel(GradArgs g)
     // flush: row partials (ordinary pass) and the objective or correction parts
     if (!g.restore) {
         float* row = g.part + (int64_t)chunk * K;
-        for (int j = threadIdx.x; j < K; j += kWG) row[j] = s.hg[j];
+        for (int j = threadIdx.x; j < K; j += kWG) row[j] = TAIL ? s.hg[j] : (float)s.hgd[j];
     }
     ob.ot = wave_sum(ob.ot);
     ob.oq = wave_sum(ob.oq);

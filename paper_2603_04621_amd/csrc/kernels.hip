@@ -48,7 +48,9 @@ size_t grad_lds_bytes(int K, int Kc, bool check, bool tail, bool det)
 {
     const size_t base = 4 * kWaves * sizeof(double);
     const size_t es = det ? 8 : 4;
-    if (!check) return base + (size_t)K * (sizeof(double) + es);
+    // ordinary passes: lam and the a x sum per row, 8 bytes (FP64 without
+    // rows beyond K, or a 64-bit integer in deterministic mode) or f32
+    if (!check) return base + (size_t)K * (sizeof(double) + ((det || !tail) ? 8 : 4));
     if (tail) return base + (size_t)K * es + (size_t)Kc * 2 * es;
     return base + (size_t)K * (sizeof(double) + es) + (size_t)Kc * 2 * es;
 }
