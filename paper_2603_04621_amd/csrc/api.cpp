@@ -693,7 +693,8 @@ static dl_status create_with(const dl_problem_desc* d, const dl_problem_opts& op
     // Problems with more rows than fit at 16 bytes but no more than fit at
     // 12 keep the 16-byte capacity and their coldest rows beyond it.
     const int64_t hes = p->det ? 8 : 4, lds_free = (int64_t)max_lds - 4 * kWaves * (int64_t)sizeof(double);
-    const int64_t kwide = lds_free / 16, knarrow = p->det ? kwide : lds_free / 12;
+    // (the multi-entry kernel keeps FP64 sums for every row in LDS)
+    const int64_t kwide = lds_free / 16, knarrow = (p->det || nf > 1) ? kwide : lds_free / 12;
     int64_t kmax = m <= kwide ? m : (m > knarrow ? knarrow : kwide);
     p->K = (int)std::max<int64_t>(0, std::min<int64_t>(m, kmax));
     const bool f64 = opts.storage == DL_F64, tail = p->K < m;

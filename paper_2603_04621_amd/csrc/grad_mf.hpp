@@ -28,6 +28,16 @@
 
 namespace dl {
 
+// adds a x to row j: FP64 LDS sums for the first K rows (every variant of
+// this kernel: an active column adds to several rows, and the LDS's f32
+// atomic add is the slow one), FP64 global accumulators beyond
+template <bool TAIL>
+__device__ __forceinline__ void mf_add(const Lds& s, const GradArgs& g, int j, double v)
+{
+    if (!TAIL || j < g.K) __hip_atomic_fetch_add(s.hgd + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else gl_add(&g.tail[j], v);
+}
+
 // plane f (0 <= f < kMfPlanes) of the coefficients and rows
 template <typename VT>
 __device__ __forceinline__ const VT* mf_a(const GradArgs& g, int f)
@@ -108,7 +118,7 @@ __device__ __forceinline__ void mf_lane_group(const GradArgs& g, const Item& it,
                 for (int f = 0; f < kMfPlanes; ++f) {
                     const double af = (double)Val<VT>::cvt(a[f][k]);
                     if (f == g.dense_f) dacc += af * x;
-                    else if (f < nf && af != 0.0) accum<false, TAIL, false>(s, g, r[f][k], af * x, 0.0, 0.0);
+                    else if (f < nf && af != 0.0) mf_add<TAIL>(s, g, r[f][k], af * x);
                 }
             } else {
                 double se = 1.0;
@@ -219,7 +229,7 @@ __device__ __forceinline__ void mf_wg_block(const GradArgs& g, const Item& it, c
                 for (int f = 0; f < g.nf; ++f) {
                     const double af = (double)Val<VT>::ld(mf_a<VT>(g, f), idx);
                     if (f == g.dense_f) dacc += af * x;
-                    else if (af != 0.0) accum<false, TAIL, false>(s, g, mf_r(g, f)[idx], af * x, 0.0, 0.0);
+                    else if (af != 0.0) mf_add<TAIL>(s, g, mf_r(g, f)[idx], af * x);
                 }
             } else {
                 double se = 1.0;
@@ -273,16 +283,14 @@ __global__ __launch_bounds__(kWG) void grad_mf_kernel(GradArgs g)
     const int K = g.K;
     s.lam = (double*)p;
     p += (size_t)K * sizeof(double);
-    // the a x sums: FP64 without rows beyond K (as in the one-entry kernels'
-    // ordinary passes), else f32
-    s.hg = (float*)p;
-    s.hgd = TAIL ? nullptr : (double*)p;
+    // the a x sums of the first K rows, FP64
+    s.hg = nullptr;
+    s.hgd = (double*)p;
     s.hc = s.hq = nullptr;
     const double gamma = g.gamma_ptr ? *g.gamma_ptr : g.gamma_val;
     for (int j = threadIdx.x; j < K; j += kWG) {
         s.lam[j] = g.lam[j];
-        if constexpr (TAIL) s.hg[j] = 0.0f;
-        else s.hgd[j] = 0.0;
+        s.hgd[j] = 0.0;
     }
     __syncthreads();
 
@@ -310,14 +318,14 @@ __global__ __launch_bounds__(kWG) void grad_mf_kernel(GradArgs g)
     }
     if (g.dense_f >= 0 && !g.restore) {
         dacc = wave_sum(dacc);
-        if ((threadIdx.x & 63) == 0 && dacc != 0.0) accum<false, TAIL, false>(s, g, g.dense_row, dacc, 0.0, 0.0);
+        if ((threadIdx.x & 63) == 0 && dacc != 0.0) mf_add<TAIL>(s, g, g.dense_row, dacc);
     }
     __syncthreads();
 
     // flush: row partials (ordinary pass) and the objective or correction parts
     if (!g.restore) {
         float* row = g.part + (int64_t)chunk * K;
-        for (int j = threadIdx.x; j < K; j += kWG) row[j] = TAIL ? s.hg[j] : (float)s.hgd[j];
+        for (int j = threadIdx.x; j < K; j += kWG) row[j] = (float)s.hgd[j];
     }
     ob.ot = wave_sum(ob.ot);
     ob.oq = wave_sum(ob.oq);
@@ -351,7 +359,8 @@ __global__ __launch_bounds__(kWG) void grad_mf_kernel(GradArgs g)
 template <typename VT, bool HASW, bool TAIL>
 static hipError_t launch_grad_mf_t(const GradArgs& a, hipStream_t s)
 {
-    const size_t lds = grad_lds_bytes(a.K, 0, false, TAIL, false);
+    // lam and an FP64 a x sum per LDS row
+    const size_t lds = 4 * kWaves * sizeof(double) + (size_t)a.K * 16;
     hipLaunchKernelGGL((grad_mf_kernel<VT, HASW, TAIL>), dim3(a.nchunks), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
