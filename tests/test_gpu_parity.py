@@ -258,6 +258,22 @@ def test_work_layouts_by_hand(O, dev, wl):
     compare(O, inst, "f64", lam_for(inst, 16, 1.0), 1e-3, grad_tol=1e-5, work_layout=wl)
 
 
+@pytest.mark.parametrize("J", [10_224, 10_225, 13_632, 13_633])
+def test_lds_capacity_edges(O, dev, J):
+    """Destinations at the edges of the LDS capacities of gfx950's 160 KB:
+    up to 10,224 rows all stay in LDS with FP64 sums in ordinary passes; one
+    more row puts the coldest beyond LDS (10,224 kept); from 13,633 rows on,
+    13,632 rows stay with f32 sums.  Ordinary and gap-check passes match the
+    oracle on each side."""
+    inst = I.large(I=40_000, J=J, capacity="greedy")
+    with gpu_problem(inst) as p:
+        rows = p.info()["lds_rows"]
+    expect = {10_224: 10_224, 10_225: 10_224, 13_632: 10_224, 13_633: 13_632}[J]
+    assert rows == expect, (J, rows)
+    compare(O, inst, "f32", lam_for(inst, 17, 2.0), 1e-3)
+    compare(O, inst, "f64", lam_for(inst, 18, 2.0), 1e-2, grad_tol=1e-5)
+
+
 def test_grad_csr_equals_csc(O, dev):
     inst = I.random_small(21, I=500, J=40, dmax=30, box_frac=0.3)
     lam = lam_for(inst, 8)
