@@ -545,6 +545,42 @@ def test_solve_trajectory_many_rows(O, dev, graph):
     assert lam_close(lam.cpu().numpy(), r_or.lam)
 
 
+@pytest.mark.parametrize("stop", ["iteration_cap", "converged"])
+def test_solve_many_rows_stops_inside_graph(O, dev, stop):
+    """J = 20,000 destinations (the scalar-step and row-step kernels): a
+    solve that ends inside a 40-iteration graph, at the iteration cap (290)
+    or at a gap tolerance first met at a later check, leaves the rest of the
+    graph without effect: iterations, g, gap and prices as the oracle's."""
+    from paper_2603_04621_amd.api import SolveSettings
+    inst = I.random_small(41, I=40_000, J=20_000, dmax=8, box_frac=0.2, capacity="greedy")
+    s = SolveSettings(gamma0=1e-2, gamma_final=1e-2, max_iters=290, check_every=10,
+                      tol_rel_gap=-1.0, max_step=1e-2, init_step=1e-4, trace=True, graph_iters=40)
+    if stop == "converged":
+        # a tolerance halfway between a check's gap and the smallest before
+        # it (a margin far above the 1e-6 the two sides' gaps agree to)
+        tr = O.solve(inst, oracle_opts(O, s)).trace[:, 1]
+        rel = tr[~np.isnan(tr)]
+        s.max_iters = 1000
+        for i in range(6, rel.size):
+            if not rel[i] < 0.99 * rel[:i].min():
+                continue
+            s.tol_rel_gap = 0.5 * (rel[i] + rel[:i].min())
+            r_or = O.solve(inst, oracle_opts(O, s))
+            if r_or.converged and r_or.iters >= 60 and r_or.iters % 40 != 0:
+                break
+        else:
+            pytest.fail("no gap tolerance met inside a graph")
+    else:
+        r_or = O.solve(inst, oracle_opts(O, s))
+    with gpu_problem(inst, "f64") as p:
+        lam, r = p.solve(s)
+    assert r.iters == r_or.iters and r.converged == r_or.converged == (stop == "converged")
+    assert r.iters % 40 != 0
+    assert abs(r.g - r_or.g) <= 1e-6 * max(1.0, abs(r_or.g))
+    assert abs(r.rel_gap - r_or.rel_gap) <= 1e-6
+    assert lam_close(lam.cpu().numpy(), r_or.lam)
+
+
 def test_solve_continuation_to_gap(O, dev):
     """gamma continuation with stage changes on the gap and on the iteration
     budget, stopping at rel_gap 1e-4; FP64 storage follows the oracle."""
