@@ -182,6 +182,32 @@ def test_grad_zipf_large_degree_config_shape(O, dev):
     compare(O, inst, "f32", lam_for(inst, 3, 2.0), 1e-3)
 
 
+@pytest.mark.parametrize("workload", ["large", "heavy"])
+def test_grad_full_size_workloads(O, dev, workload):
+    """The two timed workloads at full size, FP32 storage, default layout:
+    10M sources x 10k destinations (100,007,779 nonzeros, every row in LDS)
+    and the heavy-tailed 2M x 50k (60,145,687 nonzeros, rows beyond LDS).
+    The ordinary pass the solve runs (no x, no scalars) and the gap-check
+    pass (x and scalars) against the oracle's evaluation of every row and
+    edge, at the tolerances of the smaller cases."""
+    inst = (I.large if workload == "large" else I.heavy)(capacity="greedy")
+    lam = lam_for(inst, 17, 2.0)
+    gamma = 1e-3
+    ref = inst.rounded("f32")
+    ev = O.dual_eval(ref, lam, gamma)
+    with gpu_problem(inst) as p:
+        info = p.info()
+        grad, _, _ = p.dual_grad(torch.from_numpy(lam), gamma)
+        grad = grad.cpu().numpy()
+    assert (info["lds_rows"] == inst.m) == (workload == "large")
+    scale = np.bincount(inst.dst, weights=np.abs(ref.a * ev.x), minlength=inst.m) + np.abs(inst.b)
+    gerr = np.abs(grad - ev.grad) / np.maximum(scale, 1e-300)
+    gerr[(scale == 0) & (grad == ev.grad)] = 0.0
+    assert gerr.max() <= 1e-5, float(gerr.max())
+    del ev, grad, gerr, scale
+    compare(O, inst, "f32", lam, gamma)
+
+
 def test_grad_check_sums_partly_in_lds(O, dev):
     """J = 10k destinations, all in LDS: the gap-check pass keeps lam and the
     a x sums of every row in LDS but the c x and v^2 x^2 sums of only the
