@@ -95,6 +95,31 @@ def test_three_families_rows_beyond_lds_and_csr(O, dev):
     compare_multi(O, inst, "f64", lam_for(inst, 5, 0.5), 1e-2, g_tol=1e-12, layout="csr")
 
 
+def test_full_size_two_families_and_count_row(O, dev):
+    """The timed multi-entry workload at full size: 2M sources, two families
+    of 10k destinations and the count row (20,001 rows, 60,015,519 entries),
+    FP32, 80% simplex / 20% box blocks.  The ordinary pass (no x, no
+    scalars) and the gap check with its restoration pass against the
+    oracle's evaluation of every row and edge."""
+    inst = I.multi_family(I=2_000_000, J=10_000, families=2, count_row=True, box_frac=0.2)
+    lam = lam_for(inst, 6, 0.5)
+    gamma = 1e-3
+    ref = inst.rounded("f32")
+    ev = O.dual_eval(ref, lam, gamma)
+    with problem(inst) as p:
+        grad, _, _ = p.dual_grad(torch.from_numpy(lam), gamma)
+        grad = grad.cpu().numpy()
+    cols = np.repeat(np.arange(inst.n), np.diff(inst.colptr))
+    scale = np.bincount(inst.rowidx, weights=np.abs(ref.val * ev.x[cols]), minlength=inst.m) + \
+        np.abs(inst.b)
+    gerr = np.abs(grad - ev.grad) / np.maximum(scale, 1e-300)
+    gerr[(scale == 0) & (grad == ev.grad)] = 0.0
+    assert gerr.max() <= 1e-5, float(gerr.max())
+    del ev, grad, gerr, scale, cols
+    info = compare_multi(O, inst, "f32", lam, gamma)
+    assert info["col_entries"] == 3 and info["lds_rows"] < inst.m
+
+
 def test_iteration_norm_by_power_iteration(dev):
     """|A'|^2 of the iteration matrix (rows normalised) from the host's power
     iteration equals the largest eigenvalue of A'A'^T (within its 1e-3

@@ -182,20 +182,21 @@ def test_grad_zipf_large_degree_config_shape(O, dev):
     compare(O, inst, "f32", lam_for(inst, 3, 2.0), 1e-3)
 
 
-@pytest.mark.parametrize("workload", ["large", "heavy"])
-def test_grad_full_size_workloads(O, dev, workload):
-    """The two timed workloads at full size, FP32 storage, default layout:
-    10M sources x 10k destinations (100,007,779 nonzeros, every row in LDS)
-    and the heavy-tailed 2M x 50k (60,145,687 nonzeros, rows beyond LDS).
-    The ordinary pass the solve runs (no x, no scalars) and the gap-check
-    pass (x and scalars) against the oracle's evaluation of every row and
-    edge, at the tolerances of the smaller cases."""
+@pytest.mark.parametrize("workload,storage", [("large", "f32"), ("heavy", "f32"), ("large", "bf16")])
+def test_grad_full_size_workloads(O, dev, workload, storage):
+    """The two timed workloads at full size, default layout: 10M sources x
+    10k destinations (100,007,779 nonzeros, every row in LDS; FP32 and BF16
+    storage) and the heavy-tailed 2M x 50k (60,145,687 nonzeros, rows beyond
+    LDS; FP32).  The ordinary pass the solve runs (no x, no scalars) and the
+    gap-check pass (x and scalars) against the oracle's evaluation of every
+    row and edge on the same stored values, at the tolerances of the smaller
+    cases."""
     inst = (I.large if workload == "large" else I.heavy)(capacity="greedy")
     lam = lam_for(inst, 17, 2.0)
     gamma = 1e-3
-    ref = inst.rounded("f32")
+    ref = inst.rounded(storage)
     ev = O.dual_eval(ref, lam, gamma)
-    with gpu_problem(inst) as p:
+    with gpu_problem(inst, storage) as p:
         info = p.info()
         grad, _, _ = p.dual_grad(torch.from_numpy(lam), gamma)
         grad = grad.cpu().numpy()
@@ -205,7 +206,7 @@ def test_grad_full_size_workloads(O, dev, workload):
     gerr[(scale == 0) & (grad == ev.grad)] = 0.0
     assert gerr.max() <= 1e-5, float(gerr.max())
     del ev, grad, gerr, scale
-    compare(O, inst, "f32", lam, gamma)
+    compare(O, inst, storage, lam, gamma)
 
 
 def test_grad_check_sums_partly_in_lds(O, dev):
