@@ -107,8 +107,13 @@ def fixed_settings(gamma, iters, check_every=10, **kw):
 
 def graph_rate(p, gamma, steps, warmup, check_every=10, lam0=None):
     """(lam, outcome, seconds) of exactly `steps` graph-path iterations at
-    gamma, after an untimed warm-up solve that captures the graph."""
+    gamma, after untimed warm-up solves: one of at least `warmup` iterations
+    that captures the graph, then two of the timed length (the first solves
+    after a capture run slower by about 0.3 ms, which at 20 steps would be
+    8% of the timed region; a solve to a gap runs hundreds of iterations)."""
     p.solve(fixed_settings(gamma, max(warmup, 2 * check_every), check_every), lam0=lam0)
+    for _ in range(2):
+        p.solve(fixed_settings(gamma, steps, check_every), lam0=lam0)
     sync()
     t0 = time.perf_counter()
     lam, r = p.solve(fixed_settings(gamma, steps, check_every), lam0=lam0)
