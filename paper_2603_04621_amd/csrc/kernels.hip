@@ -122,9 +122,34 @@ hipError_t set_grad_attributes(size_t lds)
 constexpr int kRedSlices = 16;
 constexpr int kRedThreads = 64 * kRedSlices;
 
+// the per-row inputs of the finishing wave, read before the partial sums so
+// that both sets of loads are in flight together
+struct RowIn {
+    double b, lam, D, Gp, y, yp;
+    int32_t orig;
+};
+
+__device__ __forceinline__ RowIn row_inputs(const ReduceArgs& r, const int j)
+{
+    RowIn in{};
+    if (j < r.J) {
+        in.b = r.b[j];
+        in.lam = r.lam[j];
+        if (r.mode == 1) {
+            in.orig = r.orig[j];
+        } else {
+            in.D = r.D[j];
+            in.Gp = r.Gp[j];
+            in.y = r.y[j];
+            in.yp = r.yp[j];
+        }
+    }
+    return in;
+}
+
 // wave 0: per-row gradient and the block's scalar sums
 __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk, const int l, const int j,
-                                              const double (*sh)[kRedSlices][64])
+                                              const double (*sh)[kRedSlices][64], const RowIn& in)
 {
     double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (j < r.J) {
@@ -153,18 +178,18 @@ __device__ __forceinline__ void reduce_finish(const ReduceArgs& r, const int blk
             cj = take(r.J + j, 1);
             qj = take(2 * (int64_t)r.J + j, 2);
         }
-        const double bj = r.b[j];
+        const double bj = in.b;
         const double res = ax - bj;
-        S[0] = r.lam[j] * bj;
+        S[0] = in.lam * bj;
         if (r.mode == 1) {
-            r.grad_out[r.orig[j]] = res;
+            r.grad_out[in.orig] = res;
         } else {
-            const double Gj = r.D[j] * res;
+            const double Gj = in.D * res;
             r.G[j] = Gj;
             S[1] = Gj * Gj;
-            const double dg = Gj - r.Gp[j];
+            const double dg = Gj - in.Gp;
             S[2] = dg * dg;
-            const double dy = r.y[j] - r.yp[j];
+            const double dy = in.y - in.yp;
             S[3] = dy * dy;
         }
         if (r.check) {
@@ -192,6 +217,8 @@ __device__ __forceinline__ void reduce_rows(const ReduceArgs& r, const int blk)
     const int j = blk * 64 + l;
     const int planes = r.check ? 3 : 1;
     const int64_t plane = (int64_t)r.nchunks * r.K;
+    RowIn in{};
+    if (q == 0) in = row_inputs(r, j);
     for (int p = 0; p < planes; ++p) {
         double acc = 0.0;
         if (r.det && j < (p == 0 ? r.K : r.Kc)) {
@@ -226,7 +253,7 @@ __device__ __forceinline__ void reduce_rows(const ReduceArgs& r, const int blk)
         sh[p][q][l] = acc;
     }
     __syncthreads();
-    if (q == 0) reduce_finish(r, blk, l, j, sh);
+    if (q == 0) reduce_finish(r, blk, l, j, sh, in);
 }
 
 __device__ __forceinline__ void reduce_body(const ReduceArgs& r, const int blk)
@@ -515,9 +542,24 @@ constexpr int kRowThreads = 256;
 __global__ __launch_bounds__(kRowThreads) void agd_row_kernel(AgdArgs a)
 {
     const SolveState* st = a.st;
-    if (st->step_stop) return;
-    agd_rows(a, st->step_eta, st->step_beta, st->step_adv != 0, blockIdx.x * kRowThreads + threadIdx.x,
-             gridDim.x * kRowThreads);
+    // the thread's first row is read together with the step (reading it is
+    // harmless when no step is taken); further rows, if the grid is smaller
+    // than J, go through the loop
+    const int j = blockIdx.x * kRowThreads + threadIdx.x;
+    const int stride = gridDim.x * kRowThreads;
+    double yv = 0.0, gv = 0.0, lv = 0.0, dv = 0.0;
+    if (j < a.J) {
+        yv = a.y[j];
+        gv = a.G[j];
+        lv = a.lam[j];
+        dv = a.D[j];
+    }
+    const int32_t stop = st->step_stop;
+    const double eta = st->step_eta, beta = st->step_beta;
+    const bool adv = st->step_adv != 0;
+    if (stop) return;
+    if (j < a.J) agd_row(a, j, yv, gv, lv, dv, eta, beta, adv);
+    if (j + stride < a.J) agd_rows(a, eta, beta, adv, j + stride, stride);
 }
 
 // small problems: both halves in one workgroup (one launch less per iteration)
