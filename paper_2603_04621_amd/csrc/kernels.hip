@@ -370,7 +370,10 @@ hipError_t launch_eval_finish(const double* obj_part, int nchunks, const double*
 // ---------------------------------------------------------------------------
 // scalar half of the step (all threads of one workgroup): the reduced
 // scalars, the step size, the stop test and the stage logic; sc receives
-// eta, beta, advance, stop (shared memory)
+// eta, beta, advance, stop (shared memory).  TEST_DONE: the caller has not
+// tested st->done; it is read with the state (a stopped solve's partial sums
+// are read and ignored) and a stopped solve gets stop = 1 and no update.
+template <bool TEST_DONE>
 __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
 {
     SolveState* st = a.st;
@@ -379,8 +382,9 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
     // thread 0 reads the state before the reductions, so its loads overlap them
     double cur_gamma = 0.0, cur_eta = 0.0, cur_eta_cap = 0.0, cur_tm = 0.0;
     int64_t cur_k = 0, cur_ks = 0, cur_kmax = 0;
-    int32_t cur_stage = 0;
+    int32_t cur_stage = 0, cur_done = 0;
     if (threadIdx.x == 0) {
+        if (TEST_DONE) cur_done = st->done;
         cur_kmax = st->kmax;
         cur_gamma = st->gamma;
         cur_eta = st->eta;
@@ -392,7 +396,12 @@ __device__ __forceinline__ void agd_scalars(const AgdArgs& a, double* sc)
     }
     reduce_scalars(a.obj_part, a.nchunks, a.blockpart, a.nblk, v, red, a.check ? a.corr_part : nullptr);
     const SolveParams& P = a.prm;
-    if (threadIdx.x == 0) {
+    if (TEST_DONE && threadIdx.x == 0 && cur_done) {
+        sc[0] = 0.0;
+        sc[1] = 0.0;
+        sc[2] = 0.0;
+        sc[3] = 1.0;
+    } else if (threadIdx.x == 0) {
         const int64_t k = cur_k;
         const int64_t ks = cur_ks;
         const double gamma = cur_gamma;
@@ -524,11 +533,7 @@ __global__ __launch_bounds__(kScalarThreads) void agd_scalar_kernel(AgdArgs a)
 {
     SolveState* st = a.st;
     __shared__ double sc[4];
-    if (st->done) {
-        if (threadIdx.x == 0) st->step_stop = 1;
-        return;
-    }
-    agd_scalars(a, sc);
+    agd_scalars<true>(a, sc);
     if (threadIdx.x == 0) {
         st->step_eta = sc[0];
         st->step_beta = sc[1];
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(kScalarThreads) void agd_fused_kernel(AgdArgs a)
 {
     if (a.st->done) return;
     __shared__ double sc[4];
-    agd_scalars(a, sc);
+    agd_scalars<false>(a, sc);
     if (sc[3] != 0.0) return;
     agd_rows(a, sc[0], sc[1], sc[2] != 0.0, threadIdx.x, blockDim.x);
 }
@@ -594,7 +599,7 @@ __global__ __launch_bounds__(kScalarThreads) void agd_kernel_batch(const AgdArgs
     const AgdArgs a = tab[blockIdx.x];
     if (a.st->done) return;
     __shared__ double sc[4];
-    agd_scalars(a, sc);
+    agd_scalars<false>(a, sc);
     if (sc[3] != 0.0) return;
     agd_rows(a, sc[0], sc[1], sc[2] != 0.0, threadIdx.x, blockDim.x);
 }
